@@ -1,0 +1,65 @@
+"""Seeded synthetic LP workloads (inputs only; no simplex arithmetic here).
+
+Both the HIP library's tests/benchmarks and the reference oracle draw their
+inputs from this module, so it holds nothing but random-number draws.
+
+Dense generator G(m, n, seed), for  max c^T x  s.t.  A x <= b,  x >= 0:
+    rng = numpy.random.default_rng(seed)          (PCG64)
+    A   = rng.integers(1, 101, (m, n))  as float64 (integer uniform [1, 100])
+    b   = rng.uniform(1000 s, 10000 s, m), s = n / 64
+    c   = rng.integers(1, 101, n)       as float64
+drawn in that order.  A > 0 and b > 0 make every instance feasible at x = 0
+and bounded.  It stands in for the paper's own random instances, which are
+not available (Section 4 describes dense random problems of sizes 256..8192).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def dense_lp(m: int, n: int, seed: int):
+    """One dense LP (A, b, c) with the distribution described above."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(1, 101, size=(m, n)).astype(np.float64)
+    s = n / 64.0
+    b = rng.uniform(1000.0 * s, 10000.0 * s, size=m)
+    c = rng.integers(1, 101, size=n).astype(np.float64)
+    return A, b, c
+
+
+def log_uniform_int(rng, lo: int, hi: int, size=None):
+    """round(exp(U(ln lo, ln hi))) clipped to [lo, hi]."""
+    v = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=size))).astype(np.int64)
+    return np.clip(v, lo, hi)
+
+
+def batch_shapes(count: int, lo: int, hi: int, seed: int = 0):
+    """Shapes (m_i, n_i), each independently log-uniform in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    m = log_uniform_int(rng, lo, hi, size=count)
+    n = log_uniform_int(rng, lo, hi, size=count)
+    return m, n
+
+
+def batch_lps(count: int, lo: int = 32, hi: int = 1024, seed: int = 0):
+    """A batch of independent dense LPs of uneven sizes.
+
+    Shapes come from `batch_shapes(count, lo, hi, seed)`; instance i then uses
+    dense_lp(m_i, n_i, seed_i) with seed_i the i-th child of
+    numpy.random.SeedSequence(seed).
+    """
+    m, n = batch_shapes(count, lo, hi, seed)
+    children = np.random.SeedSequence(seed).spawn(count)
+    out = []
+    for i in range(count):
+        s = int(children[i].generate_state(1, dtype=np.uint64)[0] >> np.uint64(1))
+        out.append(dense_lp(int(m[i]), int(n[i]), s))
+    return out
+
+
+def poisson_arrivals(rate: float, count: int, seed: int = 0):
+    """Arrival times (s) of a Poisson process: cumulative exponential gaps."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
