@@ -1,0 +1,167 @@
+"""Benchmark: dense-tableau simplex pivots on one MI355X.
+
+Default workload: one dense LP, m = n = 8192, FP64, generator seed 0 (A
+integer uniform [1,100], b uniform [1000 s, 10000 s] with s = n/64, c integer
+uniform [1,100]).  One step = one lp_solve_dense_ex call through the C ABI:
+Table 1 build, the whole pivot loop on the device (pricing, ratio test,
+pivot-row division, rank-1 update of the (m+1) x (n+m+1) tableau) and the
+solution read-out.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0).  `value` is pivots per second over the K timed
+steps; `roofline` relates the persistent kernel's algorithmic bytes
+(16 (m+1)(n+m+1) per pivot) to its average duration measured with HIP events
+on the stream the kernel runs on; `cpu_baseline` times the CPU oracle on a
+bounded sample of the same LP (its first pivots) on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pivots/s + HBM GB/s (8192x8192 FP64); batched LPs/s; p50/p99 served latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(A, b, c, target_s: float):
+    """Oracle pivots/s on this host: time the first pivots of the same LP.
+
+    Runs the oracle with max_iter = 0 (Table 1 build only) and with max_iter
+    = K; the difference over K is the per-pivot time.  K grows until the
+    pivot part takes about `target_s` seconds (bounded sample)."""
+    import oracle
+    t0 = time.perf_counter()
+    r0 = oracle.solve(A, b, c, max_iter=0)
+    t_build = time.perf_counter() - t0
+    K = 2
+    t0 = time.perf_counter()
+    r = oracle.solve(A, b, c, max_iter=K)
+    t_k = time.perf_counter() - t0
+    per = max((t_k - t_build) / max(r.iterations, 1), 1e-9)
+    K2 = int(max(1, min(10_000, target_s / per)))
+    if K2 > K:
+        t0 = time.perf_counter()
+        r = oracle.solve(A, b, c, max_iter=K2)
+        t_k = time.perf_counter() - t0
+        K = K2
+    piv = max(r.iterations, 1)
+    rate = piv / max(t_k - t_build, 1e-9)
+    assert r0.iterations == 0
+    return {"value": rate, "unit": "pivots/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {piv} pivots of the same {A.shape[0]}x{A.shape[1]} LP "
+                      f"(oracle run with max_iter={K} minus a max_iter=0 build-only run; "
+                      f"{t_k:.1f} s total, single thread, gcc -O3)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=8192)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-iter", type=int, default=-1, help="pivot cap per solve (-1: solve to the end)")
+    ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
+              f"(one LP per GPU; see the sharding design in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1804_04737_amd import lpdense, lpgen
+
+    lpdense.load()
+    dev = torch.device("cuda:0")
+    m, n = args.m, args.n
+    log(f"generating {m}x{n} LP seed {args.seed}")
+    A, b, c = lpgen.dense_lp(m, n, args.seed)
+    tA = torch.from_numpy(A).to(dev)
+    tb = torch.from_numpy(b).to(dev)
+    tc = torch.from_numpy(c).to(dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=lpdense.SCHED_AUTO,
+                                      grid_blocks=args.grid_blocks, want_y=True, stream=stream)
+
+    for w in range(args.warmup):
+        log(f"warmup {w}")
+        r = step()
+        torch.cuda.synchronize()
+        log(f"warmup {w} done: status={lpdense.STATUS_NAMES[int(r.status.item())]} "
+            f"pivots={int(r.iterations.item())} z={float(r.obj.item())!r}")
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        results.append(step())
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pivots = [int(r.iterations.item()) for r in results]
+    statuses = [int(r.status.item()) for r in results]
+    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    total_piv = sum(pivots)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; pivots per step {pivots}; event ms {ev_ms}")
+
+    R, W = m + 1, n + m + 1
+    bytes_per_pivot = 16.0 * R * W
+    avg_ms = sum(ev_ms) / len(ev_ms)
+    achieved = bytes_per_pivot * (total_piv / args.steps) / (avg_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(A, b, c, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(total_piv / elapsed, 2),
+        "unit": "pivots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dense LP max c^T x, Ax<=b, x>=0, m={m}, n={n}, seed {args.seed}, "
+                               f"full solve from the slack basis (Dantzig, lowest-index ties)",
+                   "m": m, "n": n, "pivots_per_step": pivots[0],
+                   "status": lpdense.STATUS_NAMES[statuses[0]],
+                   "bytes_per_pivot": int(bytes_per_pivot),
+                   "max_iter": args.max_iter},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

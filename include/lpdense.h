@@ -1,0 +1,156 @@
+/*
+ * lpdense: dense-tableau simplex for AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * Problem (Coutinho et al., Section 2, eq. 1 in canonical <= form):
+ *
+ *     maximize  c^T x   subject to  A x <= b,  x >= 0,   with b >= 0,
+ *
+ * solved by the standard simplex method on the full (m+1) x (n+m+1) tableau
+ * of Table 1 (constraint rows [A_i | e_i | b_i], objective row [-c | 0 | 0]),
+ * starting from the slack basis.  One pivot (Section 2, Steps 2-5) is:
+ *   Step 2  Dantzig pricing: entering column k = the lowest index j < n+m
+ *           minimising the objective-row entry T[m,j]; optimal when
+ *           T[m,k] >= -eps_d.
+ *   Step 3  ratio test over rows i < m with T[i,k] > eps_p:
+ *           rho_i = T[i,rhs] / T[i,k]; leaving row l = lowest i minimising
+ *           rho_i; no eligible row means the LP is unbounded.
+ *   Step 4  pivot row r = T[l,:] / T[l,k] (IEEE division).
+ *   Step 5  every other row, objective row included:
+ *           T[i,j] <- fma(-T[i,k], r_j, T[i,j]) (multiplier read before the
+ *           row changes; one rounding per element).
+ * Loop order per iteration: price -> optimal? -> iteration cap? -> ratio
+ * test -> unbounded? -> pivot.  Non-finite input, or a non-finite value seen
+ * by the pricing scan or by the ratio test, gives LPD_NUMERICAL; a negative
+ * b_i gives LPD_INFEASIBLE_START before any pivot (the slack basis of
+ * Section 2 needs b >= 0).  Every result is deterministic: for the same
+ * inputs and options the outputs are bitwise identical on every call, for
+ * every schedule, grid size and batch composition.
+ *
+ * Memory and ownership.  Unless a comment says "host", every pointer argument
+ * is a DEVICE pointer on the current HIP device, and the caller owns it.
+ * Matrices are row-major with leading dimension equal to their column count.
+ * All solve calls are stream-ordered and asynchronous: they validate their
+ * arguments on the host, enqueue work on `stream` and return; outputs are
+ * valid once `stream` has completed, and the caller keeps every buffer alive
+ * until then.  Workspace is allocated and freed stream-ordered on `stream`
+ * (hipMallocAsync / hipFreeAsync) and belongs to the library.
+ *
+ * Errors.  A negative return value (lpd_error) means nothing was enqueued and
+ * no output was written.  Data-dependent outcomes are not errors: they are
+ * the lpd_status value written to the device-side `status` output.  On any
+ * status other than LPD_OPTIMAL, x / obj / y describe the last basis reached.
+ *
+ * Thread safety: calls on distinct streams may run concurrently; the library
+ * keeps no mutable global state apart from per-device launch limits that are
+ * computed once.
+ */
+#ifndef LPDENSE_H
+#define LPDENSE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Outcome of a solve, written to the device `status` output (int32). */
+typedef enum lpd_status {
+    LPD_OPTIMAL = 0,          /* no reduced cost below -eps_d */
+    LPD_UNBOUNDED = 1,        /* entering column has no entry > eps_p */
+    LPD_ITERATION_LIMIT = 2,  /* max_iter pivots done, not yet optimal */
+    LPD_INFEASIBLE_START = 3, /* some b_i < 0: slack basis infeasible */
+    LPD_NUMERICAL = 4,        /* NaN/Inf in the input or met while pivoting */
+    LPD_DEVICE_TIMEOUT = 5    /* a grid-wide barrier of the persistent kernel did not
+                                 complete within its watchdog time (about 10 s); the
+                                 outputs are undefined.  Not expected in normal use. */
+} lpd_status;
+
+/* Synchronous argument / launch errors (negative return values). */
+typedef enum lpd_error {
+    LPD_SUCCESS = 0,
+    LPD_ERR_INVALID_ARG = -1,   /* m < 1, n < 1, bad option value */
+    LPD_ERR_NULL_POINTER = -2,  /* a required pointer is NULL */
+    LPD_ERR_SIZE_OVERFLOW = -3, /* sizes overflow the index types */
+    LPD_ERR_OUT_OF_MEMORY = -4, /* workspace does not fit on the device */
+    LPD_ERR_HIP = -5,           /* a HIP runtime call or launch failed */
+    LPD_ERR_DEVICE = -6,        /* no usable gfx950 device is current */
+    LPD_ERR_TOO_LARGE = -7,     /* request exceeds a configured budget */
+    LPD_ERR_NOT_FOUND = -8      /* unknown handle or request id */
+} lpd_error;
+
+/* Defaults used when an option is left at 0 / negative. */
+#define LPD_DEFAULT_EPS 1e-9
+/* Default iteration cap: 50 * (m + n). */
+
+/* Schedules for the single-LP solve. */
+typedef enum lpd_schedule {
+    LPD_SCHED_AUTO = 0,       /* library picks (workgroup if the tableau fits in LDS) */
+    LPD_SCHED_WORKGROUP = 1,  /* one workgroup runs the whole pivot loop */
+    LPD_SCHED_GRID = 2        /* persistent cooperative grid, one grid barrier per pivot */
+} lpd_schedule;
+
+/*
+ * lp_solve_dense: solve one LP with default options.
+ *   m, n    number of constraints / structural variables (>= 1, host values)
+ *   A       m*n row-major, b length m, c length n               (device, in)
+ *   x       length n (out); obj, status: one double / one int32  (device, out)
+ *   stream  HIP stream the work is enqueued on (0 = null stream)
+ * Returns LPD_SUCCESS or a negative lpd_error.
+ */
+int lp_solve_dense(int64_t m, int64_t n, const double *A, const double *b, const double *c,
+                   double *x, double *obj, int32_t *status, hipStream_t stream);
+
+/* Problem description for lp_solve_dense_ex (all device pointers). */
+typedef struct lpd_problem {
+    int64_t m, n;
+    const double *A; /* m*n row-major */
+    const double *b; /* m */
+    const double *c; /* n */
+} lpd_problem;
+
+/* Options (host struct; zero-initialise for defaults). */
+typedef struct lpd_options {
+    double eps_d;      /* optimality tolerance (<= 0: 1e-9) */
+    double eps_p;      /* ratio-test pivot tolerance (<= 0: 1e-9) */
+    int64_t max_iter;  /* pivot cap (< 0: 50*(m+n); 0 allowed) */
+    int32_t schedule;  /* lpd_schedule */
+    int32_t grid_blocks; /* grid schedule: workgroups to launch (0: one per CU, capped by co-residency) */
+} lpd_options;
+
+/* Outputs (device pointers; NULL skips an optional output). */
+typedef struct lpd_outputs {
+    double *x;           /* n, required */
+    double *obj;         /* 1, required */
+    int32_t *status;     /* 1, required (lpd_status) */
+    double *y;           /* m, optional: duals T[m, n+i] of the final tableau */
+    int64_t *iterations; /* 1, optional: pivots performed */
+    int32_t *trace;      /* 2*trace_cap, optional: (k, l) of each pivot, in order */
+    int64_t trace_cap;   /* capacity of trace in pivots */
+    int64_t *basis;      /* m, optional: basic variable of each row (0..n+m-1) */
+    double *tableau;     /* (m+1)*(n+m+1), optional: final tableau, Table 1 layout */
+} lpd_outputs;
+
+/*
+ * lp_solve_dense_ex: solve one LP with options and optional outputs.
+ * `prob`, `opt` and `out` are host structs read during the call; `opt` may be
+ * NULL for defaults.  Same semantics, errors and ownership as lp_solve_dense.
+ */
+int lp_solve_dense_ex(const lpd_problem *prob, const lpd_options *opt, const lpd_outputs *out,
+                      hipStream_t stream);
+
+/* Device workspace (bytes) a single solve of an m x n LP allocates. */
+uint64_t lpd_workspace_bytes(int64_t m, int64_t n);
+
+/* Static strings for an lpd_error / lpd_status code ("unknown" otherwise). */
+const char *lpd_error_string(int code);
+const char *lpd_status_string(int32_t status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int lpd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPDENSE_H */

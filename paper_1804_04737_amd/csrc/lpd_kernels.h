@@ -1,0 +1,76 @@
+// Kernel parameter blocks and launch entry points shared between the host
+// runtime (lpd_api.hip) and the kernels (lpd_grid.hip, lpd_wg.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpd {
+
+// Inputs, options and outputs of one LP solve as the kernels see them.
+struct SolveArgs {
+  int64_t m, n;
+  const double* A;
+  const double* b;
+  const double* c;
+  double eps_d, eps_p;
+  int64_t max_iter;
+  // outputs (device; optional ones may be null)
+  double* x;
+  double* obj;
+  int32_t* status;
+  double* y;
+  int64_t* iterations;
+  int32_t* trace;
+  int64_t trace_cap;
+  int64_t* basis_out;
+  double* tableau_out;
+};
+
+// Reduction-barrier slot: one per workgroup and per epoch parity, 128 B apart.
+struct alignas(128) BarrierSlot {
+  double v;
+  double aux;
+  int32_t i;
+  int32_t flags;
+  uint32_t epoch;
+  uint32_t pad[25];
+};
+static_assert(sizeof(BarrierSlot) == 128, "slot must fill one 128 B line");
+
+// Device workspace of the persistent grid solve (all pointers into one allocation).
+struct GridWork {
+  int64_t ld;      // row stride of T in doubles (multiple of 32)
+  int64_t vw;      // 16-byte vectors per row that carry data: ceil((n+m)/2)
+  double* T;       // m x ld, constraint rows, columns 0..n+m-1 (RHS kept apart)
+  double* obj[2];  // objective row (ld doubles), double-buffered by pivot parity
+  double* pr[2];   // normalised pivot row of the last pivot (ld doubles), by parity
+  double* pcol[2]; // column of the entering variable, rows 0..m-1, by parity
+  double* rhs[2];  // right-hand side, rows 0..m (row m = objective value), by parity
+  int32_t* basis;  // m: basic variable of each row
+  int32_t* pos;    // n+m: row of each basic variable, -1 if nonbasic
+  BarrierSlot* slots; // 2 * nblocks
+};
+
+// Sizes of the grid workspace pieces (bytes, each rounded to 256).
+struct GridLayout {
+  int64_t ld, vw;
+  uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_slots, total;
+};
+GridLayout grid_layout(int64_t m, int64_t n, int nblocks);
+
+// Host-side launchers (return hipError_t of the launch).
+hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, int nthreads,
+                             hipStream_t stream);
+// Largest grid the persistent kernel can run co-resident with `nthreads` per block
+// and the LDS a given tableau width needs (0 if it cannot run at all).
+int grid_max_blocks(int64_t m, int64_t n, int nthreads);
+// LDS bytes the grid kernel needs for an n+m wide tableau.
+size_t grid_lds_bytes(int64_t m, int64_t n, int nthreads);
+
+// Single-workgroup solve with the tableau resident in LDS.
+size_t wg_lds_bytes(int64_t m, int64_t n);
+size_t wg_lds_limit();
+hipError_t launch_wg_solve(const SolveArgs& a, hipStream_t stream);
+
+}  // namespace lpd

@@ -1,0 +1,176 @@
+"""Thin Python binding of the lpdense C ABI (include/lpdense.h).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+the in-tree `liblpdense.so`.  PyTorch supplies device memory and the current
+HIP stream.  There is no CPU fallback: if the library is missing or cannot be
+loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblpdense.so")
+
+OPTIMAL, UNBOUNDED, ITERATION_LIMIT, INFEASIBLE_START, NUMERICAL, DEVICE_TIMEOUT = range(6)
+STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "NUMERICAL",
+                "DEVICE_TIMEOUT")
+SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID = 0, 1, 2
+
+# Exported symbols, as declared in include/lpdense.h.
+EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lpd_workspace_bytes", "lpd_error_string",
+           "lpd_status_string", "lpd_version")
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", _I64), ("n", _I64), ("A", _P), ("b", _P), ("c", _P)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
+                ("schedule", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("x", _P), ("obj", _P), ("status", _P), ("y", _P), ("iterations", _P),
+                ("trace", _P), ("trace_cap", _I64), ("basis", _P), ("tableau", _P)]
+
+
+class LpdError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} failed: {error_string(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1804_04737_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.lp_solve_dense.restype = ctypes.c_int
+    lib.lp_solve_dense.argtypes = [_I64, _I64, _P, _P, _P, _P, _P, _P, _P]
+    lib.lp_solve_dense_ex.restype = ctypes.c_int
+    lib.lp_solve_dense_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                      ctypes.POINTER(Outputs), _P]
+    lib.lpd_workspace_bytes.restype = ctypes.c_uint64
+    lib.lpd_workspace_bytes.argtypes = [_I64, _I64]
+    lib.lpd_error_string.restype = ctypes.c_char_p
+    lib.lpd_error_string.argtypes = [ctypes.c_int]
+    lib.lpd_status_string.restype = ctypes.c_char_p
+    lib.lpd_status_string.argtypes = [ctypes.c_int32]
+    lib.lpd_version.restype = ctypes.c_int
+    lib.lpd_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def error_string(code: int) -> str:
+    return load().lpd_error_string(int(code)).decode()
+
+
+def workspace_bytes(m: int, n: int) -> int:
+    return int(load().lpd_workspace_bytes(int(m), int(n)))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_dev(name, t, dtype, numel):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+
+
+def solve_dense(A, b, c, x=None, obj=None, status=None, stream=None):
+    """lp_solve_dense on device tensors; returns (x, obj, status) device tensors.
+
+    Asynchronous on `stream` (default: torch's current stream)."""
+    import torch
+    m, n = A.shape
+    _check_dev("A", A, torch.float64, m * n)
+    _check_dev("b", b, torch.float64, m)
+    _check_dev("c", c, torch.float64, n)
+    dev = A.device
+    x = torch.empty(n, dtype=torch.float64, device=dev) if x is None else x
+    obj = torch.empty(1, dtype=torch.float64, device=dev) if obj is None else obj
+    status = torch.empty(1, dtype=torch.int32, device=dev) if status is None else status
+    rc = load().lp_solve_dense(m, n, _ptr(A), _ptr(b), _ptr(c), _ptr(x), _ptr(obj), _ptr(status),
+                               _stream_handle(stream))
+    if rc != 0:
+        raise LpdError(rc, "lp_solve_dense")
+    return x, obj, status
+
+
+@dataclass
+class DenseResult:
+    x: "object"
+    obj: "object"
+    status: "object"
+    y: "object"
+    iterations: "object"
+    trace: "object"
+    basis: "object"
+    tableau: "object"
+
+
+def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
+                   schedule: int = SCHED_AUTO, grid_blocks: int = 0, want_y: bool = True,
+                   trace_cap: int = 0, want_basis: bool = False, want_tableau: bool = False,
+                   stream=None) -> DenseResult:
+    """lp_solve_dense_ex on device tensors; outputs are freshly allocated
+    device tensors (asynchronous: synchronise the stream before reading)."""
+    import torch
+    m, n = A.shape
+    _check_dev("A", A, torch.float64, m * n)
+    _check_dev("b", b, torch.float64, m)
+    _check_dev("c", c, torch.float64, n)
+    dev = A.device
+    f64, i32, i64 = torch.float64, torch.int32, torch.int64
+    res = DenseResult(
+        x=torch.empty(n, dtype=f64, device=dev),
+        obj=torch.empty(1, dtype=f64, device=dev),
+        status=torch.empty(1, dtype=i32, device=dev),
+        y=torch.empty(m, dtype=f64, device=dev) if want_y else None,
+        iterations=torch.empty(1, dtype=i64, device=dev),
+        trace=torch.empty((max(trace_cap, 0), 2), dtype=i32, device=dev) if trace_cap > 0 else None,
+        basis=torch.empty(m, dtype=i64, device=dev) if want_basis else None,
+        tableau=torch.empty((m + 1, n + m + 1), dtype=f64, device=dev) if want_tableau else None,
+    )
+    prob = Problem(m, n, A.data_ptr(), b.data_ptr(), c.data_ptr())
+    opts = Options(float(eps_d), float(eps_p), int(max_iter), int(schedule), int(grid_blocks))
+    outs = Outputs(res.x.data_ptr(), res.obj.data_ptr(), res.status.data_ptr(),
+                   res.y.data_ptr() if res.y is not None else None,
+                   res.iterations.data_ptr(),
+                   res.trace.data_ptr() if res.trace is not None else None,
+                   int(max(trace_cap, 0)),
+                   res.basis.data_ptr() if res.basis is not None else None,
+                   res.tableau.data_ptr() if res.tableau is not None else None)
+    rc = load().lp_solve_dense_ex(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(outs),
+                                  _stream_handle(stream))
+    if rc != 0:
+        raise LpdError(rc, "lp_solve_dense_ex")
+    return res

@@ -1,0 +1,61 @@
+"""C-ABI checks that need no GPU: the library builds, loads and exports every
+function include/lpdense.h declares; host-side validation rejects bad
+arguments before any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1804_04737_amd import lpdense
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "lpdense.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(l[a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for want in ("lp_solve_dense", "lp_solve_dense_ex", "lpd_workspace_bytes",
+                 "lpd_error_string", "lpd_status_string", "lpd_version"):
+        assert want in names
+    assert set(names) == set(lpdense.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lpdense.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strings_and_version():
+    lib = lpdense.load()
+    assert lib.lpd_version() >= 100
+    assert lpdense.error_string(0) == "success"
+    assert lpdense.error_string(-2) == "null pointer"
+    assert lpdense.error_string(12345) == "unknown"
+    for s, name in enumerate(lpdense.STATUS_NAMES):
+        assert lib.lpd_status_string(s).decode() == name
+    assert lib.lpd_status_string(99).decode() == "unknown"
+
+
+def test_host_validation_without_device():
+    """Invalid arguments are rejected on the host, before any HIP call."""
+    lib = lpdense.load()
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.lp_solve_dense(0, 3, dummy, dummy, dummy, dummy, dummy, dummy, None) == -1
+    assert lib.lp_solve_dense(3, -1, dummy, dummy, dummy, dummy, dummy, dummy, None) == -1
+    assert lib.lp_solve_dense(3, 3, None, dummy, dummy, dummy, dummy, dummy, None) == -2
+    assert lib.lp_solve_dense(3, 3, dummy, dummy, dummy, None, dummy, dummy, None) == -2
+    assert lib.lp_solve_dense(1 << 40, 3, dummy, dummy, dummy, dummy, dummy, dummy, None) == -3
+    assert lib.lp_solve_dense_ex(None, None, None, None) == -2
+    p = lpdense.Problem(2, 2, 0x1000, 0x1000, 0x1000)
+    o = lpdense.Outputs(0x1000, 0x1000, 0x1000, None, None, None, 5, None, None)
+    assert lib.lp_solve_dense_ex(ctypes.byref(p), None, ctypes.byref(o), None) == -2  # trace_cap > 0, no trace
+    o.trace_cap = -1
+    assert lib.lp_solve_dense_ex(ctypes.byref(p), None, ctypes.byref(o), None) == -1

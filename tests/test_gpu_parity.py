@@ -1,0 +1,135 @@
+"""GPU parity: the HIP path, called through the C ABI, reproduces the CPU
+oracle bit for bit -- status, pivot sequence, x, objective, duals, basis and
+(where requested) the whole tableau -- on both schedules, several grid sizes,
+ragged shapes, edge cases and the full-size workloads (sampled)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1804_04737_amd import lpdense, lpgen
+from tests import lp_checks
+from tests.gpu_util import announce, assert_bitwise_equal, bits, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+WG, GRID = lpdense.SCHED_WORKGROUP, lpdense.SCHED_GRID
+
+
+def _examples():
+    with open(GOLDEN) as f:
+        return json.load(f)["examples"]
+
+
+@pytest.mark.parametrize("schedule", [WG, GRID], ids=["wg", "grid"])
+@pytest.mark.parametrize("ex", _examples(), ids=lambda e: e["id"])
+def test_worked_examples(ex, schedule):
+    A, b, c = (np.array(ex[k], float) for k in ("A", "b", "c"))
+    max_iter = ex.get("max_iter", -1)
+    announce(f"worked example {ex['id']} schedule={schedule}")
+    g = gpu_solve(A, b, c, max_iter=max_iter, schedule=schedule, want_tableau=True)
+    ref = oracle.solve(A, b, c, max_iter=None if max_iter < 0 else max_iter, want_tableau=True)
+    assert_bitwise_equal(g, ref, check_tableau=True)
+    assert g.status == ex["status"] and g.trace.tolist() == ex["trace"]
+
+
+@pytest.mark.parametrize("seed", range(100))
+def test_config0_64x64_workgroup(seed):
+    """64 x 64 generator instances (the small single-LP workload), default schedule."""
+    A, b, c = lpgen.dense_lp(64, 64, seed)
+    announce(f"64x64 seed={seed} auto schedule")
+    g = gpu_solve(A, b, c, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert ref.status == oracle.OPTIMAL
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_config0_64x64_grid(seed):
+    A, b, c = lpgen.dense_lp(64, 64, seed)
+    announce(f"64x64 seed={seed} grid schedule")
+    g = gpu_solve(A, b, c, schedule=GRID, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+RAGGED = [(1, 1), (1, 9), (9, 1), (2, 3), (3, 300), (300, 3), (33, 65), (129, 257), (257, 129),
+          (500, 333), (333, 500), (640, 1281), (1000, 700), (31, 2049)]
+
+
+@pytest.mark.parametrize("m,n", RAGGED)
+def test_ragged_shapes_grid(m, n):
+    """Shapes spanning several grid-stride sweeps with ragged row / vector tails."""
+    A, b, c = lpgen.dense_lp(m, n, 7 + m + n)
+    announce(f"ragged {m}x{n} grid")
+    g = gpu_solve(A, b, c, schedule=GRID, want_tableau=m * n <= 400_000)
+    ref = oracle.solve(A, b, c, want_tableau=m * n <= 400_000)
+    assert_bitwise_equal(g, ref, check_tableau=m * n <= 400_000)
+
+
+@pytest.mark.parametrize("m,n,K", [(200, 300, 7), (700, 500, 23), (1025, 1023, 40)])
+def test_tableau_after_k_pivots(m, n, K):
+    """max_iter = K stops after K pivots; the whole tableau then matches."""
+    A, b, c = lpgen.dense_lp(m, n, 100 + K)
+    announce(f"tableau after {K} pivots {m}x{n}")
+    g = gpu_solve(A, b, c, schedule=GRID, max_iter=K, want_tableau=True)
+    ref = oracle.solve(A, b, c, max_iter=K, want_tableau=True)
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+@pytest.mark.parametrize("blocks", [1, 2, 3, 7, 64, 255, 0])
+def test_grid_size_invariance(blocks):
+    """Any grid size gives the same bits (a race would show up as a difference)."""
+    A, b, c = lpgen.dense_lp(300, 451, 5)
+    announce(f"grid blocks={blocks} 300x451")
+    g = gpu_solve(A, b, c, schedule=GRID, grid_blocks=blocks, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+@pytest.mark.parametrize("schedule", [WG, GRID], ids=["wg", "grid"])
+def test_edge_cases(schedule):
+    A = np.array([[1.0, 2.0], [3.0, 1.0]])
+    cases = {
+        "negative_b": (A, np.array([1.0, -2.0]), np.array([1.0, 1.0])),
+        "nan_A": (np.array([[1.0, np.nan], [3.0, 1.0]]), np.array([1.0, 2.0]), np.array([1.0, 1.0])),
+        "inf_c": (A, np.array([1.0, 2.0]), np.array([np.inf, 1.0])),
+        "unbounded": (np.array([[0.0, 1.0]]), np.array([1.0]), np.array([1.0, 1.0])),
+        "already_optimal": (A, np.array([1.0, 2.0]), np.array([-1.0, 0.0])),
+        "degenerate_zero_b": (A, np.array([0.0, 0.0]), np.array([1.0, 1.0])),
+    }
+    for name, (A_, b_, c_) in cases.items():
+        announce(f"edge case {name} schedule={schedule}")
+        for max_iter in (-1, 0, 1):
+            g = gpu_solve(A_, b_, c_, schedule=schedule, max_iter=max_iter, want_tableau=True)
+            ref = oracle.solve(A_, b_, c_, max_iter=None if max_iter < 0 else max_iter, want_tableau=True)
+            assert_bitwise_equal(g, ref, check_tableau=name not in ("nan_A", "inf_c"))
+
+
+def test_workgroup_and_grid_agree_and_errors():
+    A, b, c = lpgen.dense_lp(40, 50, 3)
+    announce("wg vs grid 40x50")
+    g1 = gpu_solve(A, b, c, schedule=WG, want_tableau=True)
+    g2 = gpu_solve(A, b, c, schedule=GRID, want_tableau=True)
+    assert np.array_equal(bits(g1.tableau), bits(g2.tableau))
+    import torch
+    tA = torch.zeros((400, 400), dtype=torch.float64, device="cuda")
+    tb = torch.ones(400, dtype=torch.float64, device="cuda")
+    tc = torch.ones(400, dtype=torch.float64, device="cuda")
+    with pytest.raises(lpdense.LpdError) as e:  # tableau far beyond LDS
+        lpdense.solve_dense_ex(tA, tb, tc, schedule=WG)
+    assert e.value.code == -7
+
+
+@pytest.mark.parametrize("m,n,seed", [(1024, 1024, 0), (2048, 512, 1), (512, 2048, 2)])
+def test_medium_full_solve(m, n, seed):
+    A, b, c = lpgen.dense_lp(m, n, seed)
+    announce(f"medium full solve {m}x{n}")
+    g = gpu_solve(A, b, c)
+    ref = oracle.solve(A, b, c)
+    assert_bitwise_equal(g, ref)
+    rp, rd, gap = lp_checks.residuals(A, b, c, g.x, g.y)
+    assert rp <= 1e-9 and rd <= 1e-9 and gap <= 1e-9
