@@ -63,6 +63,25 @@ def cpu_baseline(A, b, c, target_s: float):
                       f"{t_k:.1f} s total, single thread, gcc -O3)"}
 
 
+def counter_traffic(pivots_per_launch: int):
+    """HBM bytes per launch from the committed PMC summary of the solve kernel,
+    or None when the kernel sources changed since the counters were taken or
+    the launch is not the one they were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "grid_solve_kernel_dense8192_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    h = hashlib.sha256()
+    for src in d["kernel_sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != d["kernel_source_sha256"] or pivots_per_launch != d["pivots"]:
+        return None
+    return (d["fetch_size_kib"] * d["fetch_scale"] + d["write_size_kib"] * d["write_scale"]) * 1024.0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +94,10 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phases", action="store_true",
+                    help="after the timed steps, run one more solve with per-phase device timestamps")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,6 +120,16 @@ def main():
     tc = torch.from_numpy(c).to(dev)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        # Plain 1 GiB copy: its FETCH_SIZE / WRITE_SIZE readings calibrate the
+        # HBM byte counters of the solve kernel.
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copied 1 GiB for counter calibration")
 
     def step():
         return lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=lpdense.SCHED_AUTO,
@@ -130,8 +163,26 @@ def main():
     bytes_per_pivot = 16.0 * R * W
     avg_ms = sum(ev_ms) / len(ev_ms)
     achieved = bytes_per_pivot * (total_piv / args.steps) / (avg_ms / 1e3) / 1e9
+    traffic = counter_traffic(pivots[0]) if (m, n, args.seed) == (8192, 8192, 0) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 1)}
+
+    phases = None
+    if args.phases:
+        K = max(pivots)
+        r = lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, grid_blocks=args.grid_blocks,
+                                   phase_cap=K, stream=stream)
+        torch.cuda.synchronize()
+        it = int(r.iterations.item())
+        if r.phase_ticks is not None and it > 2:
+            t = r.phase_ticks.cpu().numpy()[1:it].astype(np.int64)
+            d = np.median(np.diff(t[:, :7], axis=1), axis=0) * 10e-3  # us (100 MHz clock)
+            tot = float(np.median(t[:, 6] - t[:, 0])) * 10e-3
+            phases = {"us_per_pivot_median": round(tot, 2), "pricing": round(d[0], 2),
+                      "update_wg0": round(d[1], 2), "wait_last_wg": round(d[2], 2),
+                      "release": round(d[3], 2), "detect": round(d[4], 2), "reduce": round(d[5], 2)}
+            log(f"phases (median us/pivot): {phases}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -156,7 +207,7 @@ def main():
                    "m": m, "n": n, "pivots_per_step": pivots[0],
                    "status": lpdense.STATUS_NAMES[statuses[0]],
                    "bytes_per_pivot": int(bytes_per_pivot),
-                   "max_iter": args.max_iter},
+                   "max_iter": args.max_iter, "phases_us": phases},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -127,6 +127,9 @@ int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd
   a.trace_cap = out->trace_cap;
   a.basis_out = out->basis;
   a.tableau_out = out->tableau;
+  if (out->phase_cap < 0 || (out->phase_cap > 0 && !out->phase_ticks)) return LPD_ERR_INVALID_ARG;
+  a.phase_ticks = out->phase_cap > 0 ? out->phase_ticks : nullptr;
+  a.phase_cap = out->phase_cap;
 
   const bool fits_lds = wg_lds_bytes(a.m, a.n) <= wg_lds_limit();
   if (schedule == LPD_SCHED_WORKGROUP && !fits_lds) return LPD_ERR_TOO_LARGE;

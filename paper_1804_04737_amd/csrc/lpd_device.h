@@ -68,17 +68,59 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __builtin_bit_cast(double, p);
 }
 
-__device__ __forceinline__ Cand wave_reduce(Cand c) {
-#pragma unroll
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    Cand o;
-    o.v = shfl_xor_d(c.v, m);
-    o.aux = shfl_xor_d(c.aux, m);
-    o.i = __shfl_xor(c.i, m, kWave);
-    o.flags = __shfl_xor(c.flags, m, kWave);
-    c = cand_merge(c, o);
+// ---- wave / workgroup arg-min ------------------------------------------------
+// Cross-lane moves use DPP (data-parallel primitives of the VALU) instead of
+// LDS permutes: quad permutations, row mirrors and the row broadcasts of the
+// gfx9 family carry (value, index) towards lane 63 in six steps.
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_step(double& v, int32_t& i) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = dpp_i<CTRL, ROW_MASK>(p.x);
+  p.y = dpp_i<CTRL, ROW_MASK>(p.y);
+  const double ov = __builtin_bit_cast(double, p);
+  const int32_t oi = dpp_i<CTRL, ROW_MASK>(i);
+  if (lex_less(ov, oi, v, i)) {
+    v = ov;
+    i = oi;
   }
-  return c;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_readlane(p.x, lane);
+  p.y = __builtin_amdgcn_readlane(p.y, lane);
+  return __builtin_bit_cast(double, p);
+}
+
+// Wave-wide lexicographic arg-min; all lanes must be active.  Every lane gets
+// the result (the payload `aux` of the winning lane, flags OR-ed).
+__device__ __forceinline__ Cand wave_reduce(Cand c) {
+  double v = c.v;
+  int32_t i = c.i;
+  dpp_step<0xB1, 0xF>(v, i);   // quad_perm [1,0,3,2]
+  dpp_step<0x4E, 0xF>(v, i);   // quad_perm [2,3,0,1]
+  dpp_step<0x141, 0xF>(v, i);  // row_half_mirror
+  dpp_step<0x140, 0xF>(v, i);  // row_mirror
+  dpp_step<0x142, 0xA>(v, i);  // row_bcast:15 into rows 1 and 3
+  dpp_step<0x143, 0xC>(v, i);  // row_bcast:31 into rows 2 and 3
+  Cand r;
+  r.v = readlane_d(v, 63);
+  r.i = __builtin_amdgcn_readlane(i, 63);
+  // Payload of the winner: the lowest lane holding exactly (r.v, r.i).
+  const uint64_t hit = __ballot(c.i == r.i && c.v == r.v);
+  const int lane = hit ? (int)__builtin_ctzll(hit) : 0;
+  r.aux = readlane_d(c.aux, lane);
+  r.flags = 0;
+  if (__ballot(c.flags & kFlagNonFinite)) r.flags |= kFlagNonFinite;
+  if (__ballot(c.flags & kFlagNegativeB)) r.flags |= kFlagNegativeB;
+  if (__ballot(c.flags & kFlagTimeout)) r.flags |= kFlagTimeout;
+  return r;
 }
 
 // Block-wide arg-min; every thread gets the result.  `scratch` holds at least
@@ -90,7 +132,6 @@ __device__ __forceinline__ Cand block_reduce(Cand c, Cand* scratch) {
   __syncthreads();
   if (w == 0) {
     Cand d = lane < nw ? scratch[lane] : cand_none();
-    if (lane >= nw) d.flags = 0;
     d = wave_reduce(d);
     if (lane == 0) scratch[nw] = d;
   }

@@ -26,15 +26,21 @@
 // written.  The row that was pivot row at t-1 is not rewritten during Q_{t-1}
 // (others are still reading it in P_{t-1}); its current content is the
 // normalised pivot row kept in `pr`, and Q_t writes it back.
+#include <algorithm>
+#include <cstdlib>
+
 #include "lpd_device.h"
 #include "lpd_kernels.h"
 
 namespace lpd {
 namespace {
 
-constexpr int kCandScratch = 32;
-constexpr uint64_t kWatchdogTicks = 1000000000ull;  // 10 s at 100 MHz  // LDS entries for block reductions (>= 1024/64 + 1)
+constexpr int kCandScratch = 32;  // LDS entries for block reductions (>= 1024/64 + 1)
+constexpr uint64_t kWatchdogTicks = 1000000000ull;  // 10 s of the 100 MHz real-time clock
+constexpr int kTicks = 8;         // phase_ticks entries per pivot
+constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column elements per workgroup)
 constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
+constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
 
 __device__ __forceinline__ dbl2 ld_stream(const dbl2* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, p); }
@@ -42,7 +48,8 @@ __device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontempor
 // Grid-wide lexicographic arg-min that doubles as the barrier.
 // `c` is this workgroup's reduced candidate (identical in all its threads).
 // Every workgroup returns the same global result.
-__device__ Cand grid_reduce(BarrierSlot* slots, int nb, Cand c, uint32_t epoch, Cand* scratch) {
+__device__ Cand grid_reduce(BarrierSlot* slots, int nb, Cand c, uint32_t epoch, Cand* scratch,
+                            bool diag = false, uint64_t* tk = nullptr) {
   // All of this wave's memory operations (tableau stores included) complete
   // before the workgroup barrier; thread 0's agent-scope release then makes
   // them visible to the other XCDs' caches before the slot is published.
@@ -55,7 +62,13 @@ __device__ Cand grid_reduce(BarrierSlot* slots, int nb, Cand c, uint32_t epoch, 
     s->aux = c.aux;
     s->i = c.i;
     s->flags = c.flags;
+    if (diag) s->t_arrive = __builtin_amdgcn_s_memrealtime();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (diag) {
+      // Diagnostics: time after the release, made visible by a second release.
+      s->t_pub = __builtin_amdgcn_s_memrealtime();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
     __hip_atomic_store(&s->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   Cand got = cand_none();
@@ -76,6 +89,11 @@ __device__ Cand grid_reduce(BarrierSlot* slots, int nb, Cand c, uint32_t epoch, 
     polled = true;
   }
   if (polled || threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (tk) {
+    __syncthreads();
+    if (threadIdx.x == 0) tk[5] = __builtin_amdgcn_s_memrealtime();
+  }
+  uint64_t ta = 0, tp = 0;
   for (int s = threadIdx.x; s < nb; s += blockDim.x) {
     Cand o;
     o.v = buf[s].v;
@@ -83,9 +101,26 @@ __device__ Cand grid_reduce(BarrierSlot* slots, int nb, Cand c, uint32_t epoch, 
     o.i = buf[s].i;
     o.flags = buf[s].flags;
     got = cand_merge(got, o);
+    if (tk) {
+      ta = max(ta, buf[s].t_arrive);
+      tp = max(tp, buf[s].t_pub);
+    }
+  }
+  if (tk) {
+    // Diagnostics only: latest arrival and latest publication over all workgroups.
+    for (int msk = kWave / 2; msk > 0; msk >>= 1) {
+      ta = max(ta, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, ta), msk)));
+      tp = max(tp, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, tp), msk)));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && ta) {
+      __hip_atomic_fetch_max(tk + 3, ta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_max(tk + 4, tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   }
   __syncthreads();
-  return block_reduce(got, scratch);
+  const Cand r = block_reduce(got, scratch);
+  if (tk && threadIdx.x == 0) tk[6] = __builtin_amdgcn_s_memrealtime();
+  return r;
 }
 
 // Offer objective-row entry j (value v) to the pricing arg-min.
@@ -103,11 +138,22 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
   if (a > eps_p) cand_offer(c, r / a, i, a);
 }
 
-template <int NT, int UNR>
+// MAP selects how (workgroup, thread) maps onto the flat grid-stride walk:
+//   0: workgroup b owns NT consecutive vectors per sweep step;
+//   1: each workgroup is split into NT/256 sub-groups of 256 threads that act
+//      as workgroups b, b + nb, b + 2 nb, ... (4 KiB pieces per sweep step).
+template <int NT, int MAP>
 __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   Cand* scratch = reinterpret_cast<Cand*>(smem);
   dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
+  // Capture list: elements of the entering column met during the sweep.
+  unsigned char* capb = smem + kScratchBytes + (size_t)w.vw * 16;
+  double* cap_a = reinterpret_cast<double*>(capb);
+  double* cap_r = cap_a + w.cap_cap;
+  int32_t* cap_i = reinterpret_cast<int32_t*>(cap_r + w.cap_cap);
+  int32_t* cap_count = cap_i + w.cap_cap;
+  if (threadIdx.x == 0) *cap_count = 0;
 
   const int nb = gridDim.x, tid = threadIdx.x;
   const bool leader = blockIdx.x == 0;
@@ -115,10 +161,14 @@ __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w)
   const int64_t ld = w.ld;
   const int32_t vw = (int32_t)w.vw;
   const int64_t G = (int64_t)nb * NT;
-  const int64_t gid = (int64_t)blockIdx.x * NT + tid;
+  const int64_t gid = MAP == 0 ? (int64_t)blockIdx.x * NT + tid
+                               : ((int64_t)(tid / 256) * nb + blockIdx.x) * 256 + (tid & 255);
   // Flat grid-stride walk over (row, vector): start and step in (row, vec) form.
   const int32_t i_start = (int32_t)(gid / vw), v_start = (int32_t)(gid % vw);
   const int32_t step_q = (int32_t)(G / vw), step_r = (int32_t)(G % vw);
+  // Slice of the objective / pivot rows this workgroup publishes each pivot.
+  const int32_t pub_v0 = (int32_t)((int64_t)vw * blockIdx.x / nb);
+  const int32_t pub_v1 = (int32_t)((int64_t)vw * (blockIdx.x + 1) / nb);
   uint32_t epoch = 0;
 
   // ---------------- Step 1: initial tableau (Table 1) ----------------
@@ -209,9 +259,11 @@ __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w)
   }
 
   // ---------------- pivot loop ----------------
+  const bool ticks = leader && a.phase_ticks != nullptr;
   while (status < 0) {
+    uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
+    if (tk && tid == 0) tk[0] = __builtin_amdgcn_s_memrealtime();
     const int cur = (int)(iter & 1), nxt = cur ^ 1;
-    const double* obj_cur = w.obj[cur];
     double* obj_nxt = w.obj[nxt];
     const double* rhs_cur = w.rhs[cur];
     double* rhs_nxt = w.rhs[nxt];
@@ -225,23 +277,41 @@ __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w)
     // normalised row of the previous pivot if l was pivot row then.
     const dbl2* rowl = (l == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(w.T + (int64_t)l * ld);
     Cand pc = cand_none();
-    for (int32_t v = tid; v < vw; v += NT) {
-      const dbl2 t = rowl[v];
-      const dbl2 o = reinterpret_cast<const dbl2*>(obj_cur)[v];
+    const double prhs = rhs_cur[l] / p;
+    // Objective row after this pivot, entry v; also stages r_v in LDS.
+    auto p_update = [&](int32_t v, dbl2 t, dbl2 o) -> dbl2 {
       dbl2 r, on;
       r.x = t.x / p;
       r.y = t.y / p;
       on.x = __builtin_fma(-g, r.x, o.x);
       on.y = __builtin_fma(-g, r.y, o.y);
       prow[v] = r;
-      if (leader) {
+      // Each workgroup publishes one slice of the new rows (all copies agree).
+      if (v >= pub_v0 && v < pub_v1) {
         reinterpret_cast<dbl2*>(obj_nxt)[v] = on;
         reinterpret_cast<dbl2*>(pr_cur)[v] = r;
       }
       price_offer(pc, on.x, 2 * (int64_t)v, ncols);
       price_offer(pc, on.y, 2 * (int64_t)v + 1, ncols);
+      return on;
+    };
+    const dbl2* obj_cur = reinterpret_cast<const dbl2*>(w.obj[cur]);
+    for (int32_t v0 = tid; v0 < vw; v0 += 4 * NT) {
+      dbl2 t[4], o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t v = v0 + q * NT;
+        if (v < vw) {
+          t[q] = rowl[v];
+          o[q] = obj_cur[v];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t v = v0 + q * NT;
+        if (v < vw) (void)p_update(v, t[q], o[q]);
+      }
     }
-    const double prhs = rhs_cur[l] / p;
     if (leader && tid == 0) {
       rhs_nxt[m] = __builtin_fma(-g, prhs, rhs_cur[m]);
       const int32_t leaving = w.basis[l];
@@ -254,6 +324,7 @@ __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w)
       }
     }
     pc = block_reduce(pc, scratch);  // also orders the LDS writes of prow
+    if (tk && tid == 0) tk[1] = __builtin_amdgcn_s_memrealtime();
     const int32_t kn = pc.i;
     const double gn = pc.v;
     const int32_t pflags = pc.flags;
@@ -263,54 +334,62 @@ __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w)
     {
       const int32_t kv = kn >> 1, kh = kn & 1;
       const double eps_p = a.eps_p;
+      const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
       int32_t i = i_start, v = v_start;
+      const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
+      const int64_t row_step = (int64_t)step_q * ldv;
       while (i < m) {
-        int32_t iu[UNR], vu[UNR];
-        dbl2 t[UNR];
-        double f[UNR];
-        int cnt = 0;
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          iu[u] = i;
-          vu[u] = v;
-          if (i < m) {
-            cnt = u + 1;
-            f[u] = pcol_cur[i];
-            if (i != l) {
-              const dbl2* src = (i == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(w.T + (int64_t)i * ld);
-              t[u] = ld_stream(src + v);
-            }
-          }
-          v += step_r;
-          i += step_q;
-          if (v >= vw) { v -= vw; ++i; }
+        const double f = pcol_cur[i];
+        const bool cap = (v == kv);
+        double rh = 0.0;
+        if (cap) rh = rhs_cur[i];
+        const dbl2* src = (i == lprev) ? pr_prev : rowp;
+        dbl2 t;
+        if (i != l) t = ld_stream(src + v);
+        const dbl2 r = prow[v];
+        dbl2 nv;
+        if (i == l) {
+          nv = r;
+        } else {
+          nv.x = __builtin_fma(-f, r.x, t.x);
+          nv.y = __builtin_fma(-f, r.y, t.y);
         }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          if (u < cnt) {
-            const int32_t ii = iu[u], vv = vu[u];
-            const dbl2 r = prow[vv];
-            dbl2 nv;
-            if (ii == l) {
-              nv = r;
-            } else {
-              nv.x = __builtin_fma(-f[u], r.x, t[u].x);
-              nv.y = __builtin_fma(-f[u], r.y, t[u].y);
-              st_stream(reinterpret_cast<dbl2*>(w.T + (int64_t)ii * ld) + vv, nv);
-            }
-            if (vv == kv) {
-              const double an = kh ? nv.y : nv.x;
-              const double rn = (ii == l) ? prhs : __builtin_fma(-f[u], prhs, rhs_cur[ii]);
-              pcol_nxt[ii] = an;
-              rhs_nxt[ii] = rn;
-              ratio_offer(rc, an, rn, ii, eps_p);
-            }
+        // The capture runs before this element's store is issued: waiting on
+        // its operands must not also wait for the store to complete.
+        if (cap) {
+          // New entering-column entry and right-hand side of row i; the ratio
+          // itself is formed after the sweep by the whole workgroup.
+          const double an = kh ? nv.y : nv.x;
+          const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
+          pcol_nxt[i] = an;
+          rhs_nxt[i] = rn;
+          const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
+          if (slot < w.cap_cap) {
+            cap_a[slot] = an;
+            cap_r[slot] = rn;
+            cap_i[slot] = i;
+          } else {
+            ratio_offer(rc, an, rn, i, eps_p);
           }
+        }
+        if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
+        v += step_r;
+        i += step_q;
+        rowp += row_step;
+        if (v >= vw) {
+          v -= vw;
+          ++i;
+          rowp += ldv;
         }
       }
+      __syncthreads();
+      const int32_t ncap = min(*cap_count, w.cap_cap);
+      for (int32_t e = tid; e < ncap; e += NT) ratio_offer(rc, cap_a[e], cap_r[e], cap_i[e], eps_p);
     }
     rc = block_reduce(rc, scratch);
-    const Cand gr = grid_reduce(w.slots, nb, rc, ++epoch, scratch);
+    if (tid == 0) *cap_count = 0;
+    if (tk && tid == 0) tk[2] = __builtin_amdgcn_s_memrealtime();
+    const Cand gr = grid_reduce(w.slots, nb, rc, ++epoch, scratch, a.phase_ticks != nullptr, tk);
 
     // ---- loop control (identical decision in every workgroup)
     ++iter;
@@ -368,7 +447,39 @@ __global__ void clear_slots_kernel(BarrierSlot* s, int n) {
 }
 
 constexpr int kNT = 1024;
-constexpr int kUNR = 1;
+
+// Kernel variants (thread mapping); index 0 is the default.
+typedef void (*GridKernel)(SolveArgs, GridWork);
+constexpr GridKernel kVariants[] = {grid_solve_kernel<kNT, 0>, grid_solve_kernel<kNT, 1>};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// LPD_GRID_VARIANT (tuning / diagnostics) picks a kernel variant.
+// LPD_GRID_VARIANT (tuning / diagnostics) picks the thread mapping; 0 by default.
+int variant_index(int64_t) {
+  const char* e = getenv("LPD_GRID_VARIANT");
+  const int x = e ? atoi(e) : 0;
+  return (x >= 0 && x < kNumVariants) ? x : 0;
+}
+
+int lds_limit() {
+  int dev = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  return lds_max;
+}
+
+// LDS plan of the grid kernel: reduction scratch, the normalised pivot row
+// (vw 16-byte vectors) and a capture list of up to kCapMax entries, shrunk to
+// what the LDS leaves.  Returns 0 if the pivot row alone does not fit.
+size_t lds_plan(int64_t m, int64_t n, int32_t* cap) {
+  const int64_t vw = (n + m + 1) / 2;
+  const size_t base = kScratchBytes + (size_t)vw * 16 + 16;
+  const size_t limit = (size_t)lds_limit();
+  if (base > limit) return 0;
+  const size_t c = std::min<size_t>(kCapMax, (limit - base) / kCapEntryBytes);
+  *cap = (int32_t)c;
+  return base + c * kCapEntryBytes;
+}
 
 }  // namespace
 
@@ -395,20 +506,19 @@ GridLayout grid_layout(int64_t m, int64_t n, int nblocks) {
 }
 
 size_t grid_lds_bytes(int64_t m, int64_t n, int /*nthreads*/) {
-  const int64_t vw = (n + m + 1) / 2;
-  return kScratchBytes + (size_t)vw * 16;
+  int32_t cap = 0;
+  return lds_plan(m, n, &cap);
 }
 
 int grid_max_blocks(int64_t m, int64_t n, int nthreads) {
   (void)nthreads;
-  const size_t lds = grid_lds_bytes(m, n, kNT);
-  int dev = 0;
+  int32_t cap = 0;
+  const size_t lds = lds_plan(m, n, &cap);
+  if (lds == 0) return 0;
+  int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
-  int lds_max = 0, ncu = 0;
-  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (lds > (size_t)lds_max) return 0;
-  auto fn = grid_solve_kernel<kNT, kUNR>;
+  auto fn = kVariants[variant_index((n + m + 1) / 2)];
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0;
@@ -434,14 +544,15 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
   w.basis = reinterpret_cast<int32_t*>(base + L.off_basis);
   w.pos = reinterpret_cast<int32_t*>(base + L.off_pos);
   w.slots = reinterpret_cast<BarrierSlot*>(base + L.off_slots);
+  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap);
+  if (lds == 0) return hipErrorInvalidValue;
 
   const int nslots = 2 * nblocks;
   clear_slots_kernel<<<(nslots + 255) / 256, 256, 0, stream>>>(w.slots, nslots);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  const size_t lds = grid_lds_bytes(a.m, a.n, kNT);
-  auto fn = grid_solve_kernel<kNT, kUNR>;
+  auto fn = kVariants[variant_index(L.vw)];
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   SolveArgs args = a;

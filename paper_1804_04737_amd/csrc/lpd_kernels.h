@@ -25,6 +25,8 @@ struct SolveArgs {
   int64_t trace_cap;
   int64_t* basis_out;
   double* tableau_out;
+  uint64_t* phase_ticks;
+  int64_t phase_cap;
 };
 
 // Reduction-barrier slot: one per workgroup and per epoch parity, 128 B apart.
@@ -34,7 +36,10 @@ struct alignas(128) BarrierSlot {
   int32_t i;
   int32_t flags;
   uint32_t epoch;
-  uint32_t pad[25];
+  uint32_t pad0;
+  uint64_t t_arrive;  // device real-time clock at arrival (diagnostics)
+  uint64_t t_pub;     // ... after the release that precedes publication (diagnostics)
+  uint32_t pad[20];
 };
 static_assert(sizeof(BarrierSlot) == 128, "slot must fill one 128 B line");
 
@@ -50,6 +55,7 @@ struct GridWork {
   int32_t* basis;  // m: basic variable of each row
   int32_t* pos;    // n+m: row of each basic variable, -1 if nonbasic
   BarrierSlot* slots; // 2 * nblocks
+  int32_t cap_cap;     // capacity of the LDS capture list (entries)
 };
 
 // Sizes of the grid workspace pieces (bytes, each rounded to 256).

@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
 
 class Outputs(ctypes.Structure):
     _fields_ = [("x", _P), ("obj", _P), ("status", _P), ("y", _P), ("iterations", _P),
-                ("trace", _P), ("trace_cap", _I64), ("basis", _P), ("tableau", _P)]
+                ("trace", _P), ("trace_cap", _I64), ("basis", _P), ("tableau", _P),
+                ("phase_ticks", _P), ("phase_cap", _I64)]
 
 
 class LpdError(RuntimeError):
@@ -135,12 +136,13 @@ class DenseResult:
     trace: "object"
     basis: "object"
     tableau: "object"
+    phase_ticks: "object" = None
 
 
 def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
                    schedule: int = SCHED_AUTO, grid_blocks: int = 0, want_y: bool = True,
                    trace_cap: int = 0, want_basis: bool = False, want_tableau: bool = False,
-                   stream=None) -> DenseResult:
+                   phase_cap: int = 0, stream=None) -> DenseResult:
     """lp_solve_dense_ex on device tensors; outputs are freshly allocated
     device tensors (asynchronous: synchronise the stream before reading)."""
     import torch
@@ -159,6 +161,7 @@ def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter:
         trace=torch.empty((max(trace_cap, 0), 2), dtype=i32, device=dev) if trace_cap > 0 else None,
         basis=torch.empty(m, dtype=i64, device=dev) if want_basis else None,
         tableau=torch.empty((m + 1, n + m + 1), dtype=f64, device=dev) if want_tableau else None,
+        phase_ticks=torch.zeros((phase_cap, 8), dtype=i64, device=dev) if phase_cap > 0 else None,
     )
     prob = Problem(m, n, A.data_ptr(), b.data_ptr(), c.data_ptr())
     opts = Options(float(eps_d), float(eps_p), int(max_iter), int(schedule), int(grid_blocks))
@@ -168,7 +171,9 @@ def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter:
                    res.trace.data_ptr() if res.trace is not None else None,
                    int(max(trace_cap, 0)),
                    res.basis.data_ptr() if res.basis is not None else None,
-                   res.tableau.data_ptr() if res.tableau is not None else None)
+                   res.tableau.data_ptr() if res.tableau is not None else None,
+                   res.phase_ticks.data_ptr() if res.phase_ticks is not None else None,
+                   int(max(phase_cap, 0)))
     rc = load().lp_solve_dense_ex(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(outs),
                                   _stream_handle(stream))
     if rc != 0:
