@@ -149,6 +149,43 @@ typedef struct lpd_outputs {
 int lp_solve_dense_ex(const lpd_problem *prob, const lpd_options *opt, const lpd_outputs *out,
                       hipStream_t stream);
 
+/* Options of a batched solve (host struct; zero-initialise for defaults). */
+typedef struct lpd_batch_options {
+    double eps_d;            /* as lpd_options, for every LP (<= 0: 1e-9) */
+    double eps_p;
+    int64_t max_iter;        /* per LP; < 0: 50*(m_i+n_i); 0 allowed */
+    int32_t team_size;       /* workgroups per team for large LPs (0: autotune table, 1: no teams) */
+    int32_t grid_blocks;     /* workgroups of the launch (0: one per CU) */
+    int64_t team_min_bytes;  /* tableau bytes from which an LP is solved by a team
+                                (0: autotune table; < 0: never) */
+    int64_t *iterations;     /* device, count entries, optional: pivots of each LP */
+} lpd_batch_options;
+
+/*
+ * lp_solve_batch: solve `count` independent LPs (max c_i^T x s.t. A_i x <= b_i,
+ * x >= 0) in one persistent launch.  Each LP follows exactly the rules of
+ * lp_solve_dense and its x / obj / status are bit-identical to what
+ * lp_solve_dense returns for it alone, for any batch composition and order.
+ *   count              number of LPs (>= 1)
+ *   m, n               host arrays of count sizes (each >= 1)
+ *   A_pack, b_pack,    device arrays holding every LP's A (row-major, m_i*n_i),
+ *   c_pack               b (m_i) and c (n_i) back to back
+ *   A_off, b_off,      host arrays of count element offsets into the packs
+ *   c_off
+ *   x_pack, x_off      device output pack and host offsets (n_i entries each)
+ *   obj, status        device outputs, count entries each
+ *   opt                may be NULL (defaults)
+ * LPs whose tableau fits in LDS are solved by one workgroup in LDS; larger
+ * ones by one workgroup over HBM, or by a team of workgroups if the tableau
+ * is at least team_min_bytes.  Large LPs are started first.  Returns
+ * LPD_SUCCESS or a negative lpd_error; asynchronous and stream-ordered like
+ * lp_solve_dense.  Host arrays are only read during the call.
+ */
+int lp_solve_batch(int32_t count, const int64_t *m, const int64_t *n, const double *A_pack,
+                   const int64_t *A_off, const double *b_pack, const int64_t *b_off, const double *c_pack,
+                   const int64_t *c_off, double *x_pack, const int64_t *x_off, double *obj, int32_t *status,
+                   const lpd_batch_options *opt, hipStream_t stream);
+
 /* Device workspace (bytes) a single solve of an m x n LP allocates. */
 uint64_t lpd_workspace_bytes(int64_t m, int64_t n);
 

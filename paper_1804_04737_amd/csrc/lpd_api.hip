@@ -2,11 +2,19 @@
 // validation, schedule choice, stream-ordered workspace and kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
 
+#include "lpd_batch.h"
 #include "lpd_kernels.h"
 #include "lpdense.h"
 
@@ -88,6 +96,50 @@ int resolve_options(const lpd_problem* prob, const lpd_options* opt, SolveArgs* 
   return LPD_SUCCESS;
 }
 
+// Batch schedule parameters from the autotune table (written by
+// paper_1804_04737_amd/autotune.py next to the library, or the file named by
+// LPD_AUTOTUNE_FILE); built-in defaults when there is none.  Read once.
+struct Tuning {
+  int team_size = 16;
+  int64_t team_min_bytes = 4 << 20;
+};
+
+const Tuning& tuning() {
+  static std::once_flag once;
+  static Tuning t;
+  std::call_once(once, [] {
+    std::string path;
+    if (const char* e = std::getenv("LPD_AUTOTUNE_FILE")) {
+      path = e;
+    } else {
+      Dl_info info;
+      if (dladdr(reinterpret_cast<void*>(&lp_solve_batch), &info) && info.dli_fname) {
+        path = info.dli_fname;
+        const size_t slash = path.rfind('/');
+        path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/autotune.json";
+      }
+    }
+    std::ifstream f(path);
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    auto num = [&](const char* key, int64_t dflt) -> int64_t {
+      size_t p = s.find(std::string("\"") + key + "\"");
+      if (p == std::string::npos) return dflt;
+      p = s.find(':', p);
+      if (p == std::string::npos) return dflt;
+      char* end = nullptr;
+      const long long v = std::strtoll(s.c_str() + p + 1, &end, 10);
+      return end == s.c_str() + p + 1 ? dflt : (int64_t)v;
+    };
+    const int64_t ts = num("team_size", t.team_size);
+    if (ts >= 1 && ts <= 1024) t.team_size = (int)ts;
+    t.team_min_bytes = num("team_min_bytes", t.team_min_bytes);
+  });
+  return t;
+}
+
 int hip_err(hipError_t e) {
   if (e == hipSuccess) return LPD_SUCCESS;
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return LPD_ERR_OUT_OF_MEMORY;
@@ -163,6 +215,79 @@ int lp_solve_dense(int64_t m, int64_t n, const double* A, const double* b, const
   o.obj = obj;
   o.status = status;
   return lp_solve_dense_ex(&p, nullptr, &o, stream);
+}
+
+int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const double* A_pack, const int64_t* A_off,
+                   const double* b_pack, const int64_t* b_off, const double* c_pack, const int64_t* c_off,
+                   double* x_pack, const int64_t* x_off, double* obj, int32_t* status,
+                   const lpd_batch_options* opt, hipStream_t stream) {
+  if (count < 1) return LPD_ERR_INVALID_ARG;
+  if (!m || !n || !A_pack || !A_off || !b_pack || !b_off || !c_pack || !c_off || !x_pack || !x_off || !obj ||
+      !status)
+    return LPD_ERR_NULL_POINTER;
+  for (int32_t i = 0; i < count; ++i) {
+    if (m[i] < 1 || n[i] < 1) return LPD_ERR_INVALID_ARG;
+    if (m[i] > kMaxDim || n[i] > kMaxDim || m[i] + n[i] + 1 > kMaxDim) return LPD_ERR_SIZE_OVERFLOW;
+    if (A_off[i] < 0 || b_off[i] < 0 || c_off[i] < 0 || x_off[i] < 0) return LPD_ERR_INVALID_ARG;
+  }
+  DeviceInfo dev;
+  int rc = device_info(&dev);
+  if (rc != LPD_SUCCESS) return rc;
+
+  double eps_d = LPD_DEFAULT_EPS, eps_p = LPD_DEFAULT_EPS;
+  int64_t max_iter = -1, team_min = 0;
+  int team_size = 0, nblocks = dev.ncu;
+  int64_t* iterations = nullptr;
+  if (opt) {
+    if (std::isnan(opt->eps_d) || std::isnan(opt->eps_p) || std::isinf(opt->eps_d) || std::isinf(opt->eps_p))
+      return LPD_ERR_INVALID_ARG;
+    if (opt->eps_d > 0) eps_d = opt->eps_d;
+    if (opt->eps_p > 0) eps_p = opt->eps_p;
+    max_iter = opt->max_iter;
+    if (opt->team_size < 0 || opt->grid_blocks < 0) return LPD_ERR_INVALID_ARG;
+    team_size = opt->team_size;
+    team_min = opt->team_min_bytes;
+    if (opt->grid_blocks > 0) nblocks = opt->grid_blocks;
+    iterations = opt->iterations;
+  }
+  if (team_size == 0) team_size = tuning().team_size;
+  if (team_min == 0) team_min = tuning().team_min_bytes;
+
+  BatchPlan P = plan_batch(count, m, n, team_size, team_min, nblocks);
+  if (!P.ok) return LPD_ERR_TOO_LARGE;
+  const int maxb = batch_max_blocks(P.lds_bytes);
+  if (maxb <= 0) return LPD_ERR_TOO_LARGE;
+  if (nblocks > maxb) P = plan_batch(count, m, n, team_size, team_min, maxb);
+
+  std::vector<BatchItem> items((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    SolveArgs& a = items[(size_t)i].a;
+    a.m = m[i];
+    a.n = n[i];
+    a.A = A_pack + A_off[i];
+    a.b = b_pack + b_off[i];
+    a.c = c_pack + c_off[i];
+    a.eps_d = eps_d;
+    a.eps_p = eps_p;
+    a.max_iter = max_iter >= 0 ? max_iter : 50 * (m[i] + n[i]);
+    a.x = x_pack + x_off[i];
+    a.obj = obj + i;
+    a.status = status + i;
+    a.iterations = iterations ? iterations + i : nullptr;
+    items[(size_t)i].klass = P.klass[(size_t)i];
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && P.total > total_b) return LPD_ERR_OUT_OF_MEMORY;
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, P.total, stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hip_err(e);
+  }
+  e = launch_batch(P, items, ws, stream);
+  const hipError_t ef = hipFreeAsync(ws, stream);
+  if (e != hipSuccess) return hip_err(e);
+  return hip_err(ef);
 }
 
 uint64_t lpd_workspace_bytes(int64_t m, int64_t n) {

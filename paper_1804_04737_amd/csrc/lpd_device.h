@@ -91,6 +91,12 @@ __device__ __forceinline__ void dpp_step(double& v, int32_t& i) {
   }
 }
 
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   int2 p = __builtin_bit_cast(int2, v);
   p.x = __builtin_amdgcn_readlane(p.x, lane);
@@ -136,7 +142,13 @@ __device__ __forceinline__ Cand block_reduce(Cand c, Cand* scratch) {
     if (lane == 0) scratch[nw] = d;
   }
   __syncthreads();
-  return scratch[nw];
+  // The result is the same in every lane: make that explicit (scalar registers).
+  Cand r = scratch[nw];
+  r.v = __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, r.v)));
+  r.aux = __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, r.aux)));
+  r.i = __builtin_amdgcn_readfirstlane(r.i);
+  r.flags = __builtin_amdgcn_readfirstlane(r.flags);
+  return r;
 }
 
 }  // namespace lpd

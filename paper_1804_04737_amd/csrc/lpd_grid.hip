@@ -1,444 +1,20 @@
-// Persistent cooperative-grid solve of one dense LP (gfx950).
-//
-// The whole simplex loop of Coutinho et al. (Section 2, Steps 1-5, iterated
-// as in Section 3) runs inside one kernel launch: no host round trip per
-// pivot.  One grid-wide synchronisation per pivot:
-//
-//   P_t  (every workgroup, redundantly)  read the current pivot row l_t and
-//        the objective row; divide the pivot row by the pivot (Step 4) into
-//        LDS; update the objective row (Step 5 for row m) and price it
-//        (Step 2 of the next pivot) -> k_{t+1}, g_{t+1}.  Workgroup 0 also
-//        publishes the new objective row, the normalised pivot row, the
-//        objective value and the basis bookkeeping.
-//   Q_t  (all workgroups, flat grid-stride over constraint rows x 16-byte
-//        vectors)  T[i,:] <- fma(-f_i, r, T[i,:]) for i != l_t (Step 5),
-//        streamed once with non-temporal 128-bit loads and stores.  The
-//        thread that owns element (i, k_{t+1}) also forms the new right-hand
-//        side of row i and its ratio (Step 3 of the next pivot) and keeps the
-//        lexicographic minimum.
-//   R_t  grid reduction barrier: every workgroup publishes its ratio
-//        candidate, waits for all others and reduces them -> l_{t+1}.
-//
-// Layout in HBM: constraint rows 0..m-1 of the tableau, row-major, stride
-// `ld` (multiple of 32 doubles); the objective row, the right-hand side and
-// the entering column live in separate double-buffered vectors so that every
-// workgroup can read the previous pivot's values while the new ones are
-// written.  The row that was pivot row at t-1 is not rewritten during Q_{t-1}
-// (others are still reading it in P_{t-1}); its current content is the
-// normalised pivot row kept in `pr`, and Q_t writes it back.
+// Single-LP persistent cooperative-grid solve: one team made of every
+// workgroup of the launch (the algorithm is in lpd_team.h).
 #include <algorithm>
 #include <cstdlib>
 
-#include "lpd_device.h"
-#include "lpd_kernels.h"
+#include "lpd_team.h"
 
 namespace lpd {
 namespace {
 
-constexpr int kCandScratch = 32;  // LDS entries for block reductions (>= 1024/64 + 1)
-constexpr uint64_t kWatchdogTicks = 1000000000ull;  // 10 s of the 100 MHz real-time clock
-constexpr int kTicks = 8;         // phase_ticks entries per pivot
-constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column elements per workgroup)
-constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
-constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
-
-__device__ __forceinline__ dbl2 ld_stream(const dbl2* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, p); }
-
-// Grid-wide lexicographic arg-min that doubles as the barrier.
-// `c` is this workgroup's reduced candidate (identical in all its threads).
-// Every workgroup returns the same global result.
-__device__ Cand grid_reduce(BarrierSlot* slots, int nb, Cand c, uint32_t epoch, Cand* scratch,
-                            bool diag = false, uint64_t* tk = nullptr) {
-  // All of this wave's memory operations (tableau stores included) complete
-  // before the workgroup barrier; thread 0's agent-scope release then makes
-  // them visible to the other XCDs' caches before the slot is published.
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  BarrierSlot* buf = slots + (size_t)(epoch & 1u) * nb;
-  if (threadIdx.x == 0) {
-    BarrierSlot* s = buf + blockIdx.x;
-    s->v = c.v;
-    s->aux = c.aux;
-    s->i = c.i;
-    s->flags = c.flags;
-    if (diag) s->t_arrive = __builtin_amdgcn_s_memrealtime();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (diag) {
-      // Diagnostics: time after the release, made visible by a second release.
-      s->t_pub = __builtin_amdgcn_s_memrealtime();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    }
-    __hip_atomic_store(&s->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  Cand got = cand_none();
-  bool polled = false;
-  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  for (int s = threadIdx.x; s < nb; s += blockDim.x) {
-    // Epochs only grow; a slot written for a later epoch also counts as arrived
-    // (its payload lives in the other parity buffer).
-    while ((int32_t)(__hip_atomic_load(&buf[s].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
-      __builtin_amdgcn_s_sleep(1);
-      // Watchdog: a barrier that has not completed after kWatchdogTicks of the
-      // 100 MHz real-time counter reports a timeout instead of waiting forever.
-      if (__builtin_amdgcn_s_memrealtime() - t0 > kWatchdogTicks) {
-        got.flags |= kFlagTimeout;
-        break;
-      }
-    }
-    polled = true;
-  }
-  if (polled || threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  if (tk) {
-    __syncthreads();
-    if (threadIdx.x == 0) tk[5] = __builtin_amdgcn_s_memrealtime();
-  }
-  uint64_t ta = 0, tp = 0;
-  for (int s = threadIdx.x; s < nb; s += blockDim.x) {
-    Cand o;
-    o.v = buf[s].v;
-    o.aux = buf[s].aux;
-    o.i = buf[s].i;
-    o.flags = buf[s].flags;
-    got = cand_merge(got, o);
-    if (tk) {
-      ta = max(ta, buf[s].t_arrive);
-      tp = max(tp, buf[s].t_pub);
-    }
-  }
-  if (tk) {
-    // Diagnostics only: latest arrival and latest publication over all workgroups.
-    for (int msk = kWave / 2; msk > 0; msk >>= 1) {
-      ta = max(ta, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, ta), msk)));
-      tp = max(tp, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, tp), msk)));
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0 && ta) {
-      __hip_atomic_fetch_max(tk + 3, ta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_max(tk + 4, tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  }
-  __syncthreads();
-  const Cand r = block_reduce(got, scratch);
-  if (tk && threadIdx.x == 0) tk[6] = __builtin_amdgcn_s_memrealtime();
-  return r;
-}
-
-// Offer objective-row entry j (value v) to the pricing arg-min.
-__device__ __forceinline__ void price_offer(Cand& c, double v, int64_t j, int64_t ncols) {
-  if (j < ncols) {
-    if (!is_finite(v)) c.flags |= kFlagNonFinite;
-    if (!__builtin_isnan(v)) cand_offer(c, v, (int32_t)j, 0.0);
-  }
-}
-
-// Ratio-test contribution of row i with new entering-column value `a` and
-// new right-hand side `r` (Step 3 of the next pivot).
-__device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t i, double eps_p) {
-  if (!is_finite(a) || !is_finite(r)) c.flags |= kFlagNonFinite;
-  if (a > eps_p) cand_offer(c, r / a, i, a);
-}
-
-// MAP selects how (workgroup, thread) maps onto the flat grid-stride walk:
-//   0: workgroup b owns NT consecutive vectors per sweep step;
-//   1: each workgroup is split into NT/256 sub-groups of 256 threads that act
-//      as workgroups b, b + nb, b + 2 nb, ... (4 KiB pieces per sweep step).
 template <int NT, int MAP>
 __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  Cand* scratch = reinterpret_cast<Cand*>(smem);
-  dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
-  // Capture list: elements of the entering column met during the sweep.
-  unsigned char* capb = smem + kScratchBytes + (size_t)w.vw * 16;
-  double* cap_a = reinterpret_cast<double*>(capb);
-  double* cap_r = cap_a + w.cap_cap;
-  int32_t* cap_i = reinterpret_cast<int32_t*>(cap_r + w.cap_cap);
-  int32_t* cap_count = cap_i + w.cap_cap;
-  if (threadIdx.x == 0) *cap_count = 0;
-
-  const int nb = gridDim.x, tid = threadIdx.x;
-  const bool leader = blockIdx.x == 0;
-  const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m;
-  const int64_t ld = w.ld;
-  const int32_t vw = (int32_t)w.vw;
-  const int64_t G = (int64_t)nb * NT;
-  const int64_t gid = MAP == 0 ? (int64_t)blockIdx.x * NT + tid
-                               : ((int64_t)(tid / 256) * nb + blockIdx.x) * 256 + (tid & 255);
-  // Flat grid-stride walk over (row, vector): start and step in (row, vec) form.
-  const int32_t i_start = (int32_t)(gid / vw), v_start = (int32_t)(gid % vw);
-  const int32_t step_q = (int32_t)(G / vw), step_r = (int32_t)(G % vw);
-  // Slice of the objective / pivot rows this workgroup publishes each pivot.
-  const int32_t pub_v0 = (int32_t)((int64_t)vw * blockIdx.x / nb);
-  const int32_t pub_v1 = (int32_t)((int64_t)vw * (blockIdx.x + 1) / nb);
   uint32_t epoch = 0;
-
-  // ---------------- Step 1: initial tableau (Table 1) ----------------
-  int32_t flags = 0;
-  {
-    int32_t i = i_start, v = v_start;
-    while (i < m) {
-      const int32_t j0 = 2 * v, j1 = 2 * v + 1;
-      const double* Ai = a.A + (int64_t)i * n;
-      dbl2 t;
-      t.x = j0 < n ? Ai[j0] : (j0 == n + i ? 1.0 : 0.0);
-      t.y = j1 < n ? Ai[j1] : (j1 == n + i ? 1.0 : 0.0);
-      if (!is_finite(t.x) || !is_finite(t.y)) flags |= kFlagNonFinite;
-      st_stream(reinterpret_cast<dbl2*>(w.T + (int64_t)i * ld) + v, t);
-      v += step_r;
-      i += step_q;
-      if (v >= vw) { v -= vw; ++i; }
-    }
-  }
-  for (int64_t v = gid; v < vw; v += G) {
-    const int64_t j0 = 2 * v, j1 = 2 * v + 1;
-    dbl2 o;
-    o.x = j0 < n ? -a.c[j0] : 0.0;
-    o.y = j1 < n ? -a.c[j1] : 0.0;
-    if (!is_finite(o.x) || !is_finite(o.y)) flags |= kFlagNonFinite;
-    reinterpret_cast<dbl2*>(w.obj[0])[v] = o;
-  }
-  for (int64_t i = gid; i <= m; i += G) {
-    double bi = 0.0;
-    if (i < m) {
-      bi = a.b[i];
-      if (!is_finite(bi)) flags |= kFlagNonFinite;
-      if (bi < 0.0) flags |= kFlagNegativeB;
-      w.basis[i] = (int32_t)(n + i);
-    }
-    w.rhs[0][i] = bi;
-  }
-  for (int64_t j = gid; j < ncols; j += G) w.pos[j] = j < n ? -1 : (int32_t)(j - n);
-
-  int32_t status = -1;
-  int64_t iter = 0;
-  int32_t lprev = -1;  // pivot row of the last pivot done (-1: none)
-  int32_t fpar = 0;    // parity of the current objective / rhs buffers
-  {
-    Cand f0 = cand_none();
-    f0.flags = flags;
-    f0 = block_reduce(f0, scratch);
-    const Cand gf = grid_reduce(w.slots, nb, f0, ++epoch, scratch);
-    if (gf.flags & kFlagTimeout) status = kDeviceTimeout;
-    else if (gf.flags & kFlagNonFinite) status = kNumerical;
-    else if (gf.flags & kFlagNegativeB) status = kInfeasibleStart;
-  }
-
-  // ---------------- Step 2 on the initial objective row ----------------
-  int32_t k = -1, l = -1;
-  double g = 0.0, p = 1.0;
-  if (status < 0) {
-    Cand pc = cand_none();
-    const dbl2* o = reinterpret_cast<const dbl2*>(w.obj[0]);
-    for (int32_t v = tid; v < vw; v += NT) {
-      const dbl2 ov = o[v];
-      price_offer(pc, ov.x, 2 * (int64_t)v, ncols);
-      price_offer(pc, ov.y, 2 * (int64_t)v + 1, ncols);
-    }
-    pc = block_reduce(pc, scratch);
-    if (pc.flags & kFlagNonFinite) status = kNumerical;
-    else if (pc.v >= -a.eps_d) status = kOptimal;
-    else if (a.max_iter == 0) status = kIterLimit;
-    k = pc.i;
-    g = pc.v;
-  }
-  // ---------------- Step 3 on the initial tableau ----------------
-  if (status < 0) {
-    Cand rc = cand_none();
-    for (int64_t i = gid; i < m; i += G) {
-      const double aik = w.T[i * ld + k];
-      const double r = w.rhs[0][i];
-      w.pcol[0][i] = aik;
-      ratio_offer(rc, aik, r, (int32_t)i, a.eps_p);
-    }
-    rc = block_reduce(rc, scratch);
-    const Cand gr = grid_reduce(w.slots, nb, rc, ++epoch, scratch);
-    if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
-    else if (gr.flags & kFlagNonFinite) status = kNumerical;
-    else if (gr.i == kNoIndex) status = kUnbounded;
-    l = gr.i;
-    p = gr.aux;
-  }
-
-  // ---------------- pivot loop ----------------
-  const bool ticks = leader && a.phase_ticks != nullptr;
-  while (status < 0) {
-    uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
-    if (tk && tid == 0) tk[0] = __builtin_amdgcn_s_memrealtime();
-    const int cur = (int)(iter & 1), nxt = cur ^ 1;
-    double* obj_nxt = w.obj[nxt];
-    const double* rhs_cur = w.rhs[cur];
-    double* rhs_nxt = w.rhs[nxt];
-    const double* pcol_cur = w.pcol[cur];
-    double* pcol_nxt = w.pcol[nxt];
-    double* pr_cur = w.pr[cur];
-    const dbl2* pr_prev = reinterpret_cast<const dbl2*>(w.pr[nxt]);
-
-    // ---- P_t: Step 4 (pivot row / pivot, into LDS), Step 5 on the objective
-    // row, Step 2 for the next pivot.  Row l's current content is the
-    // normalised row of the previous pivot if l was pivot row then.
-    const dbl2* rowl = (l == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(w.T + (int64_t)l * ld);
-    Cand pc = cand_none();
-    const double prhs = rhs_cur[l] / p;
-    // Objective row after this pivot, entry v; also stages r_v in LDS.
-    auto p_update = [&](int32_t v, dbl2 t, dbl2 o) -> dbl2 {
-      dbl2 r, on;
-      r.x = t.x / p;
-      r.y = t.y / p;
-      on.x = __builtin_fma(-g, r.x, o.x);
-      on.y = __builtin_fma(-g, r.y, o.y);
-      prow[v] = r;
-      // Each workgroup publishes one slice of the new rows (all copies agree).
-      if (v >= pub_v0 && v < pub_v1) {
-        reinterpret_cast<dbl2*>(obj_nxt)[v] = on;
-        reinterpret_cast<dbl2*>(pr_cur)[v] = r;
-      }
-      price_offer(pc, on.x, 2 * (int64_t)v, ncols);
-      price_offer(pc, on.y, 2 * (int64_t)v + 1, ncols);
-      return on;
-    };
-    const dbl2* obj_cur = reinterpret_cast<const dbl2*>(w.obj[cur]);
-    for (int32_t v0 = tid; v0 < vw; v0 += 4 * NT) {
-      dbl2 t[4], o[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int32_t v = v0 + q * NT;
-        if (v < vw) {
-          t[q] = rowl[v];
-          o[q] = obj_cur[v];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int32_t v = v0 + q * NT;
-        if (v < vw) (void)p_update(v, t[q], o[q]);
-      }
-    }
-    if (leader && tid == 0) {
-      rhs_nxt[m] = __builtin_fma(-g, prhs, rhs_cur[m]);
-      const int32_t leaving = w.basis[l];
-      w.pos[leaving] = -1;
-      w.pos[k] = l;
-      w.basis[l] = k;
-      if (iter < a.trace_cap && a.trace) {
-        a.trace[2 * iter] = k;
-        a.trace[2 * iter + 1] = l;
-      }
-    }
-    pc = block_reduce(pc, scratch);  // also orders the LDS writes of prow
-    if (tk && tid == 0) tk[1] = __builtin_amdgcn_s_memrealtime();
-    const int32_t kn = pc.i;
-    const double gn = pc.v;
-    const int32_t pflags = pc.flags;
-
-    // ---- Q_t: Step 5 on every constraint row, fused with Step 3 for k_{t+1}.
-    Cand rc = cand_none();
-    {
-      const int32_t kv = kn >> 1, kh = kn & 1;
-      const double eps_p = a.eps_p;
-      const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
-      int32_t i = i_start, v = v_start;
-      const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
-      const int64_t row_step = (int64_t)step_q * ldv;
-      while (i < m) {
-        const double f = pcol_cur[i];
-        const bool cap = (v == kv);
-        double rh = 0.0;
-        if (cap) rh = rhs_cur[i];
-        const dbl2* src = (i == lprev) ? pr_prev : rowp;
-        dbl2 t;
-        if (i != l) t = ld_stream(src + v);
-        const dbl2 r = prow[v];
-        dbl2 nv;
-        if (i == l) {
-          nv = r;
-        } else {
-          nv.x = __builtin_fma(-f, r.x, t.x);
-          nv.y = __builtin_fma(-f, r.y, t.y);
-        }
-        // The capture runs before this element's store is issued: waiting on
-        // its operands must not also wait for the store to complete.
-        if (cap) {
-          // New entering-column entry and right-hand side of row i; the ratio
-          // itself is formed after the sweep by the whole workgroup.
-          const double an = kh ? nv.y : nv.x;
-          const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
-          pcol_nxt[i] = an;
-          rhs_nxt[i] = rn;
-          const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
-          if (slot < w.cap_cap) {
-            cap_a[slot] = an;
-            cap_r[slot] = rn;
-            cap_i[slot] = i;
-          } else {
-            ratio_offer(rc, an, rn, i, eps_p);
-          }
-        }
-        if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
-        v += step_r;
-        i += step_q;
-        rowp += row_step;
-        if (v >= vw) {
-          v -= vw;
-          ++i;
-          rowp += ldv;
-        }
-      }
-      __syncthreads();
-      const int32_t ncap = min(*cap_count, w.cap_cap);
-      for (int32_t e = tid; e < ncap; e += NT) ratio_offer(rc, cap_a[e], cap_r[e], cap_i[e], eps_p);
-    }
-    rc = block_reduce(rc, scratch);
-    if (tid == 0) *cap_count = 0;
-    if (tk && tid == 0) tk[2] = __builtin_amdgcn_s_memrealtime();
-    const Cand gr = grid_reduce(w.slots, nb, rc, ++epoch, scratch, a.phase_ticks != nullptr, tk);
-
-    // ---- loop control (identical decision in every workgroup)
-    ++iter;
-    lprev = l;
-    fpar = (int)(iter & 1);
-    if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
-    else if (pflags & kFlagNonFinite) status = kNumerical;
-    else if (gn >= -a.eps_d) status = kOptimal;
-    else if (iter == a.max_iter) status = kIterLimit;
-    else if (gr.flags & kFlagNonFinite) status = kNumerical;
-    else if (gr.i == kNoIndex) status = kUnbounded;
-    k = kn;
-    g = gn;
-    l = gr.i;
-    p = gr.aux;
-  }
-
-  // ---------------- solution read-out ----------------
-  const double* rhs_f = w.rhs[fpar];
-  const double* obj_f = w.obj[fpar];
-  const double* pr_last = w.pr[fpar ^ 1];  // normalised row of the last pivot
-  for (int64_t j = gid; j < n; j += G) {
-    const int32_t r = w.pos[j];
-    a.x[j] = r >= 0 ? rhs_f[r] : 0.0;
-  }
-  if (a.y)
-    for (int64_t i = gid; i < m; i += G) a.y[i] = obj_f[n + i];
-  if (a.basis_out)
-    for (int64_t i = gid; i < m; i += G) a.basis_out[i] = w.basis[i];
-  if (a.tableau_out) {
-    const int64_t W = (int64_t)ncols + 1;
-    for (int64_t e = gid; e < (int64_t)(m + 1) * W; e += G) {
-      const int64_t i = e / W, j = e - i * W;
-      double val;
-      if (j == ncols) val = rhs_f[i];
-      else if (i == m) val = obj_f[j];
-      else if (i == lprev) val = pr_last[j];
-      else val = w.T[i * ld + j];
-      a.tableau_out[e] = val;
-    }
-  }
-  if (leader && tid == 0) {
-    *a.obj = rhs_f[m];
-    *a.status = status;
-    if (a.iterations) *a.iterations = iter;
-  }
+  const Team tm{(int)blockIdx.x, (int)gridDim.x, w.slots, &epoch};
+  team_solve<NT, MAP>(a, w, tm, smem);
 }
-
-inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Clears the barrier slots of a fresh workspace (stream-ordered, no memset node).
 __global__ void clear_slots_kernel(BarrierSlot* s, int n) {
@@ -483,28 +59,6 @@ size_t lds_plan(int64_t m, int64_t n, int32_t* cap) {
 
 }  // namespace
 
-GridLayout grid_layout(int64_t m, int64_t n, int nblocks) {
-  GridLayout L{};
-  L.vw = (n + m + 1) / 2;
-  L.ld = round_up(2 * L.vw, 32);
-  uint64_t off = 0;
-  auto take = [&](uint64_t bytes) {
-    const uint64_t o = off;
-    off += (uint64_t)round_up((int64_t)bytes, 256);
-    return o;
-  };
-  L.off_T = take((uint64_t)m * L.ld * 8);
-  L.off_obj = take(2ull * L.ld * 8);
-  L.off_pr = take(2ull * L.ld * 8);
-  L.off_pcol = take(2ull * (uint64_t)m * 8);
-  L.off_rhs = take(2ull * (uint64_t)(m + 1) * 8);
-  L.off_basis = take((uint64_t)m * 4);
-  L.off_pos = take((uint64_t)(n + m) * 4);
-  L.off_slots = take(2ull * nblocks * sizeof(BarrierSlot));
-  L.total = off;
-  return L;
-}
-
 size_t grid_lds_bytes(int64_t m, int64_t n, int /*nthreads*/) {
   int32_t cap = 0;
   return lds_plan(m, n, &cap);
@@ -530,21 +84,9 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
                              hipStream_t stream) {
   (void)nthreads;
   const GridLayout L = grid_layout(a.m, a.n, nblocks);
-  unsigned char* base = static_cast<unsigned char*>(workspace);
-  GridWork w{};
-  w.ld = L.ld;
-  w.vw = L.vw;
-  w.T = reinterpret_cast<double*>(base + L.off_T);
-  for (int q = 0; q < 2; ++q) {
-    w.obj[q] = reinterpret_cast<double*>(base + L.off_obj) + q * L.ld;
-    w.pr[q] = reinterpret_cast<double*>(base + L.off_pr) + q * L.ld;
-    w.pcol[q] = reinterpret_cast<double*>(base + L.off_pcol) + q * a.m;
-    w.rhs[q] = reinterpret_cast<double*>(base + L.off_rhs) + q * (a.m + 1);
-  }
-  w.basis = reinterpret_cast<int32_t*>(base + L.off_basis);
-  w.pos = reinterpret_cast<int32_t*>(base + L.off_pos);
-  w.slots = reinterpret_cast<BarrierSlot*>(base + L.off_slots);
+  GridWork w = make_grid_work(L, a.m, workspace);
   const size_t lds = lds_plan(a.m, a.n, &w.cap_cap);
+  w.lds_vecs = (int32_t)L.vw;
   if (lds == 0) return hipErrorInvalidValue;
 
   const int nslots = 2 * nblocks;

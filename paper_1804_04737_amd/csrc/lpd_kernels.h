@@ -56,6 +56,7 @@ struct GridWork {
   int32_t* pos;    // n+m: row of each basic variable, -1 if nonbasic
   BarrierSlot* slots; // 2 * nblocks
   int32_t cap_cap;     // capacity of the LDS capture list (entries)
+  int32_t lds_vecs;    // capacity of the LDS pivot-row buffer (16-byte vectors, >= vw)
 };
 
 // Sizes of the grid workspace pieces (bytes, each rounded to 256).
@@ -63,7 +64,50 @@ struct GridLayout {
   int64_t ld, vw;
   uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_slots, total;
 };
-GridLayout grid_layout(int64_t m, int64_t n, int nblocks);
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// Workspace of one team solve of an m x n LP by `nblocks` workgroups.
+__host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblocks) {
+  GridLayout L{};
+  L.vw = (n + m + 1) / 2;
+  L.ld = round_up(2 * L.vw, 32);
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off += (uint64_t)round_up((int64_t)bytes, 256);
+    return o;
+  };
+  L.off_T = take((uint64_t)m * L.ld * 8);
+  L.off_obj = take(2ull * L.ld * 8);
+  L.off_pr = take(2ull * L.ld * 8);
+  L.off_pcol = take(2ull * (uint64_t)m * 8);
+  L.off_rhs = take(2ull * (uint64_t)(m + 1) * 8);
+  L.off_basis = take((uint64_t)m * 4);
+  L.off_pos = take((uint64_t)(n + m) * 4);
+  L.off_slots = take(2ull * nblocks * sizeof(BarrierSlot));
+  L.total = off;
+  return L;
+}
+
+// Pointers of a GridWork carved out of `workspace` by layout L (LDS fields unset).
+__host__ __device__ inline GridWork make_grid_work(const GridLayout& L, int64_t m, void* workspace) {
+  unsigned char* base = static_cast<unsigned char*>(workspace);
+  GridWork w{};
+  w.ld = L.ld;
+  w.vw = L.vw;
+  w.T = reinterpret_cast<double*>(base + L.off_T);
+  for (int q = 0; q < 2; ++q) {
+    w.obj[q] = reinterpret_cast<double*>(base + L.off_obj) + q * L.ld;
+    w.pr[q] = reinterpret_cast<double*>(base + L.off_pr) + q * L.ld;
+    w.pcol[q] = reinterpret_cast<double*>(base + L.off_pcol) + q * m;
+    w.rhs[q] = reinterpret_cast<double*>(base + L.off_rhs) + q * (m + 1);
+  }
+  w.basis = reinterpret_cast<int32_t*>(base + L.off_basis);
+  w.pos = reinterpret_cast<int32_t*>(base + L.off_pos);
+  w.slots = reinterpret_cast<BarrierSlot*>(base + L.off_slots);
+  return w;
+}
 
 // Host-side launchers (return hipError_t of the launch).
 hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, int nthreads,

@@ -20,8 +20,8 @@ STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "
 SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID = 0, 1, 2
 
 # Exported symbols, as declared in include/lpdense.h.
-EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lpd_workspace_bytes", "lpd_error_string",
-           "lpd_status_string", "lpd_version")
+EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lpd_workspace_bytes",
+           "lpd_error_string", "lpd_status_string", "lpd_version")
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -40,6 +40,12 @@ class Outputs(ctypes.Structure):
     _fields_ = [("x", _P), ("obj", _P), ("status", _P), ("y", _P), ("iterations", _P),
                 ("trace", _P), ("trace_cap", _I64), ("basis", _P), ("tableau", _P),
                 ("phase_ticks", _P), ("phase_cap", _I64)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
+                ("team_size", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("team_min_bytes", _I64), ("iterations", _P)]
 
 
 class LpdError(RuntimeError):
@@ -64,6 +70,9 @@ def load(path: str = LIB_PATH):
     lib.lp_solve_dense_ex.restype = ctypes.c_int
     lib.lp_solve_dense_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                       ctypes.POINTER(Outputs), _P]
+    lib.lp_solve_batch.restype = ctypes.c_int
+    lib.lp_solve_batch.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                   ctypes.POINTER(BatchOptions), _P]
     lib.lpd_workspace_bytes.restype = ctypes.c_uint64
     lib.lpd_workspace_bytes.argtypes = [_I64, _I64]
     lib.lpd_error_string.restype = ctypes.c_char_p
@@ -179,3 +188,72 @@ def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter:
     if rc != 0:
         raise LpdError(rc, "lp_solve_dense_ex")
     return res
+
+
+@dataclass
+class PackedBatch:
+    """A batch of LPs packed into device arrays, with host offset tables, and
+    the device outputs lp_solve_batch fills."""
+    m: "object"        # host int64 arrays
+    n: "object"
+    A_off: "object"
+    b_off: "object"
+    c_off: "object"
+    x_off: "object"
+    A: "object"        # device float64 packs
+    b: "object"
+    c: "object"
+    x: "object"
+    obj: "object"
+    status: "object"
+    iterations: "object"
+
+    @property
+    def count(self) -> int:
+        return len(self.m)
+
+    def x_of(self, i):
+        return self.x[int(self.x_off[i]): int(self.x_off[i]) + int(self.n[i])]
+
+
+def pack_batch(lps, device="cuda") -> PackedBatch:
+    """Pack host (A, b, c) numpy triples into device arrays (one copy each)."""
+    import numpy as np
+    import torch
+    m = np.array([a.shape[0] for a, _, _ in lps], dtype=np.int64)
+    n = np.array([a.shape[1] for a, _, _ in lps], dtype=np.int64)
+    def offs(sizes):
+        o = np.zeros(len(sizes), dtype=np.int64)
+        o[1:] = np.cumsum(sizes)[:-1]
+        return o
+    A_off, b_off, c_off = offs(m * n), offs(m), offs(n)
+    A = np.concatenate([np.ascontiguousarray(a, dtype=np.float64).ravel() for a, _, _ in lps])
+    b = np.concatenate([np.asarray(bb, dtype=np.float64) for _, bb, _ in lps])
+    c = np.concatenate([np.asarray(cc, dtype=np.float64) for _, _, cc in lps])
+    dev = torch.device(device)
+    cnt = len(lps)
+    return PackedBatch(m, n, A_off, b_off, c_off, c_off.copy(),
+                       torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev), torch.from_numpy(c).to(dev),
+                       torch.empty(int(n.sum()), dtype=torch.float64, device=dev),
+                       torch.empty(cnt, dtype=torch.float64, device=dev),
+                       torch.empty(cnt, dtype=torch.int32, device=dev),
+                       torch.empty(cnt, dtype=torch.int64, device=dev))
+
+
+def solve_batch(pb: PackedBatch, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
+                team_size: int = 0, team_min_bytes: int = 0, grid_blocks: int = 0, stream=None) -> PackedBatch:
+    """lp_solve_batch on a PackedBatch (asynchronous; outputs land in pb)."""
+    import numpy as np
+    def hp(a):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    opts = BatchOptions(float(eps_d), float(eps_p), int(max_iter), int(team_size), int(grid_blocks),
+                        int(team_min_bytes), pb.iterations.data_ptr())
+    m = np.ascontiguousarray(pb.m, dtype=np.int64)
+    n = np.ascontiguousarray(pb.n, dtype=np.int64)
+    rc = load().lp_solve_batch(pb.count, hp(m), hp(n), pb.A.data_ptr(), hp(pb.A_off), pb.b.data_ptr(),
+                               hp(pb.b_off), pb.c.data_ptr(), hp(pb.c_off), pb.x.data_ptr(), hp(pb.x_off),
+                               pb.obj.data_ptr(), pb.status.data_ptr(), ctypes.byref(opts),
+                               _stream_handle(stream))
+    if rc != 0:
+        raise LpdError(rc, "lp_solve_batch")
+    return pb

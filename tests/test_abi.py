@@ -59,3 +59,18 @@ def test_host_validation_without_device():
     assert lib.lp_solve_dense_ex(ctypes.byref(p), None, ctypes.byref(o), None) == -2  # trace_cap > 0, no trace
     o.trace_cap = -1
     assert lib.lp_solve_dense_ex(ctypes.byref(p), None, ctypes.byref(o), None) == -1
+
+
+def test_batch_host_validation_without_device():
+    lib = lpdense.load()
+    import numpy as np
+    d = ctypes.c_void_p(0x1000)
+    one = np.array([3], dtype=np.int64)
+    zero = np.array([0], dtype=np.int64)
+    neg = np.array([-1], dtype=np.int64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    f = lib.lp_solve_batch
+    assert f(0, p(one), p(one), d, p(zero), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -1
+    assert f(1, p(zero), p(one), d, p(zero), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -1
+    assert f(1, p(one), p(one), None, p(zero), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -2
+    assert f(1, p(one), p(one), d, p(neg), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -1

@@ -1,0 +1,54 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default grid: one 1024-thread workgroup per CU).
+
+The oracle cannot run thousands of pivots at 8192 x 8192 inside a test, so:
+  * the first K pivots are compared exactly: the GPU and the oracle both run
+    with max_iter = K and return their whole tableaux; sampled rows (plus the
+    objective row and every row that was a pivot row) must agree bit for bit;
+  * the full GPU solve must reproduce the oracle's first K pivots in its
+    trace, end OPTIMAL, and satisfy properties that hold at any size: primal
+    and dual feasibility and a zero duality gap within 1e-9, and
+    complementary slackness.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1804_04737_amd import lpgen
+from tests import lp_checks
+from tests.gpu_util import announce, bits, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8192, 8192), (4096, 4096), (8192, 1024), (1024, 8192), (2048, 8192)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_first_pivots_bitwise(m, n):
+    A, b, c = lpgen.dense_lp(m, n, 0)
+    K = 3
+    announce(f"full size {m}x{n}: first {K} pivots with tableau")
+    g = gpu_solve(A, b, c, max_iter=K, want_tableau=True)
+    ref = oracle.solve(A, b, c, max_iter=K, want_tableau=True)
+    assert g.status == ref.status == oracle.ITERATION_LIMIT
+    assert np.array_equal(g.trace, ref.trace)
+    rng = np.random.default_rng(m * 7 + n)
+    rows = np.unique(np.concatenate([rng.integers(0, m, 64), ref.trace[:, 1], [m]]))
+    assert np.array_equal(bits(g.tableau[rows]), bits(ref.tableau[rows]))
+    assert np.array_equal(bits(g.tableau[:, -1]), bits(ref.tableau[:, -1]))  # whole RHS column
+    assert np.array_equal(bits(g.x), bits(ref.x)) and np.array_equal(bits(g.y), bits(ref.y))
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_full_solve_properties(m, n):
+    A, b, c = lpgen.dense_lp(m, n, 0)
+    K = 3
+    announce(f"full size {m}x{n}: complete solve")
+    g = gpu_solve(A, b, c, trace_cap=50 * (m + n))
+    ref = oracle.solve(A, b, c, max_iter=K)
+    assert g.status == oracle.OPTIMAL
+    assert np.array_equal(g.trace[:K], ref.trace)
+    rp, rd, gap = lp_checks.residuals(A, b, c, g.x, g.y)
+    assert rp <= 1e-9 and rd <= 1e-9 and gap <= 1e-9, (rp, rd, gap)
+    assert lp_checks.complementary_slackness(A, b, c, g.x, g.y) <= 1e-9
+    assert abs(float(c @ g.x) - g.obj) <= 1e-9 * abs(g.obj)
