@@ -82,6 +82,66 @@ def counter_traffic(pivots_per_launch: int):
     return (d["fetch_size_kib"] * d["fetch_scale"] + d["write_size_kib"] * d["write_scale"]) * 1024.0
 
 
+def batch_bench(args):
+    """Batched workload: one lp_solve_batch call on 1024 LPs with m, n
+    log-uniform in [32, 1024] (seed 0) per step, against solving the same
+    resident LPs one lp_solve_dense_ex call at a time on the same stream."""
+    import numpy as np
+    import torch
+
+    from paper_1804_04737_amd import lpdense, lpgen
+    lpdense.load()
+    lps = lpgen.batch_lps(args.batch_count, 32, 1024, args.seed)
+    pb = lpdense.pack_batch(lps)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    kw = dict(team_size=args.team_size, team_min_bytes=args.team_min_bytes, stream=stream)
+    for _ in range(args.warmup):
+        lpdense.solve_batch(pb, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lpdense.solve_batch(pb, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    piv = pb.iterations.cpu().numpy()
+    st = pb.status.cpu().numpy()
+    R = pb.m + 1
+    W = pb.n + pb.m + 1
+    bytes_step = float(np.sum(piv * 16.0 * R * W))
+    lps_s = args.batch_count * args.steps / el
+    log(f"batched: {el * 1e3 / args.steps:.2f} ms/step, {lps_s:.1f} LPs/s, statuses {np.bincount(st)}")
+    # One LP per call, same resident inputs, same stream.
+    views = []
+    for i in range(pb.count):
+        m, n = int(pb.m[i]), int(pb.n[i])
+        a0, b0, c0 = int(pb.A_off[i]), int(pb.b_off[i]), int(pb.c_off[i])
+        views.append((pb.A[a0:a0 + m * n].view(m, n), pb.b[b0:b0 + m], pb.c[c0:c0 + n]))
+    for v in views[:8]:
+        lpdense.solve_dense_ex(*v, want_y=False, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in views:
+        lpdense.solve_dense_ex(*v, want_y=False, stream=stream)
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t0
+    single_lps_s = pb.count / el1
+    log(f"one at a time: {el1 * 1e3:.1f} ms for {pb.count} LPs, {single_lps_s:.1f} LPs/s")
+    out = {
+        "metric": METRIC, "value": round(lps_s, 2), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched: {args.batch_count} dense LPs, m and n log-uniform in [32, 1024], "
+                               f"seed {args.seed}, one lp_solve_batch call per step",
+                   "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / args.steps), 1),
+                   "effective_GBps": round(bytes_step / (el / args.steps) / 1e9, 1),
+                   "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
+                   "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
+                   "team_size": args.team_size, "team_min_bytes": args.team_min_bytes},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,12 +158,19 @@ def main():
                     help="after the timed steps, run one more solve with per-phase device timestamps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
+    ap.add_argument("--workload", choices=["dense", "batch"], default="dense")
+    ap.add_argument("--batch-count", type=int, default=1024)
+    ap.add_argument("--team-size", type=int, default=0, help="batch: workgroups per team (0: autotune table)")
+    ap.add_argument("--team-min-bytes", type=int, default=0, help="batch: team threshold (0: autotune table)")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
               f"(one LP per GPU; see the sharding design in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return batch_bench(args)
 
     import numpy as np
     import torch

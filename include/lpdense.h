@@ -154,11 +154,16 @@ typedef struct lpd_batch_options {
     double eps_d;            /* as lpd_options, for every LP (<= 0: 1e-9) */
     double eps_p;
     int64_t max_iter;        /* per LP; < 0: 50*(m_i+n_i); 0 allowed */
-    int32_t team_size;       /* workgroups per team for large LPs (0: autotune table, 1: no teams) */
+    int32_t team_size;       /* workgroups per team for large LPs: > 1 one fixed size for
+                                all of them, 1 no teams, 0 the autotune table's choice
+                                (built-in default: sized per LP, see below) */
     int32_t grid_blocks;     /* workgroups of the launch (0: one per CU) */
     int64_t team_min_bytes;  /* tableau bytes from which an LP is solved by a team
                                 (0: autotune table; < 0: never) */
     int64_t *iterations;     /* device, count entries, optional: pivots of each LP */
+    int64_t team_bytes_per_wg; /* team_size 0: an LP of B tableau bytes gets a team of
+                                  the largest power of two <= B / team_bytes_per_wg
+                                  workgroups (0: autotune table) */
 } lpd_batch_options;
 
 /*
@@ -185,6 +190,92 @@ int lp_solve_batch(int32_t count, const int64_t *m, const int64_t *n, const doub
                    const int64_t *A_off, const double *b_pack, const int64_t *b_off, const double *c_pack,
                    const int64_t *c_off, double *x_pack, const int64_t *x_off, double *obj, int32_t *status,
                    const lpd_batch_options *opt, hipStream_t stream);
+
+/*
+ * Serving runtime (continuous batching).  A server owns one HIP stream on
+ * `device` and a worker thread.  LPs submitted from any host thread wait in
+ * arrival order; one is admitted (made resident in HBM) as soon as its
+ * footprint fits in what the budget has left and a resident slot is free.
+ * Admission never lets the footprints of resident LPs exceed the budget.
+ * The worker repeats epochs: admit what fits, then run one batched launch
+ * (the schedule of lp_solve_batch) in which every resident LP advances by at
+ * most `pivots_per_epoch` pivots, its tableau staying in HBM between epochs
+ * (an LP whose tableau fits in LDS is solved to the end within one epoch).
+ * LPs that finished leave, their memory returns to the budget and their
+ * completion is queued.  Requests that arrive while others run therefore
+ * share the device with them.  Each LP performs exactly the pivots of its own
+ * lp_solve_dense call, so x / obj / status / iterations are bit-identical to
+ * a solve of it alone, whatever else is resident.
+ *
+ * Footprint of an m x n request: every device byte it holds while resident,
+ * the tableau workspace (8 (m+1)(n+m+1) bytes, rows padded to 32 doubles)
+ * plus a copy of A, b, c and x.  LPs whose tableau fits in LDS need no
+ * tableau workspace.
+ */
+typedef struct lpd_server lpd_server;
+
+/* Server options (host struct; zero-initialise for defaults). */
+typedef struct lpd_server_options {
+    double eps_d;              /* as lpd_options (<= 0: 1e-9) */
+    double eps_p;
+    int64_t max_iter;          /* per LP (0 or < 0: 50*(m+n)) */
+    int64_t pivots_per_epoch;  /* pivots each resident LP may do per launch (<= 0: 32) */
+    int32_t max_resident;      /* most LPs resident at once (<= 0: 4096) */
+    int32_t reserved;
+    int64_t team_min_bytes;    /* as lpd_batch_options (0: autotune table) */
+    int64_t team_bytes_per_wg; /* as lpd_batch_options (0: autotune table); teams are
+                                  always sized per LP */
+} lpd_server_options;
+
+/* One finished request, as returned by lpd_server_poll. */
+typedef struct lpd_completion {
+    int64_t id;          /* value lpd_server_submit returned */
+    int32_t status;      /* lpd_status, or a negative lpd_error if the request failed
+                            (e.g. LPD_ERR_OUT_OF_MEMORY, LPD_ERR_HIP) */
+    int32_t reserved;
+    double obj;          /* objective value c^T x */
+    int64_t iterations;  /* pivots performed */
+    int64_t m, n;
+    double *x;           /* the caller's x_out buffer, now holding x (host) */
+    double t_arrive;     /* seconds since server creation: submit returned ... */
+    double t_admit;      /* ... admitted to the device ... */
+    double t_done;       /* ... result in x_out and completion queued */
+} lpd_completion;
+
+/* Counters of a server (host struct). */
+typedef struct lpd_server_stats {
+    int64_t submitted, completed, epochs;
+    int64_t resident, waiting;  /* at the last admission step */
+    uint64_t used_bytes;        /* footprint of the resident LPs now */
+    uint64_t peak_bytes;        /* largest used_bytes ever reached */
+    uint64_t budget_bytes;
+} lpd_server_stats;
+
+/* Creates a server on HIP device `device` with a footprint budget in bytes.
+ * `opt` may be NULL.  Returns NULL if the device is not a usable gfx950 or a
+ * device allocation fails. */
+lpd_server *lpd_server_create(int device, uint64_t budget_bytes, const lpd_server_options *opt);
+
+/* Queues one LP.  A, b, c (m*n row-major, m, n) and x_out (n) are HOST
+ * arrays owned by the caller; they must stay valid, and A, b, c unchanged,
+ * until the completion of this request has been returned by lpd_server_poll.
+ * Returns the request id (> 0), or a negative lpd_error: LPD_ERR_INVALID_ARG
+ * (m or n < 1), LPD_ERR_NULL_POINTER, LPD_ERR_SIZE_OVERFLOW,
+ * LPD_ERR_TOO_LARGE (footprint above the whole budget), LPD_ERR_NOT_FOUND
+ * (null or stopping server).  Thread-safe. */
+int64_t lpd_server_submit(lpd_server *server, int64_t m, int64_t n, const double *A, const double *b,
+                          const double *c, double *x_out);
+
+/* Moves up to `max` completions, oldest first, into `out` (host array) and
+ * returns how many; never blocks.  Thread-safe. */
+int lpd_server_poll(lpd_server *server, lpd_completion *out, int max);
+
+/* Copies the server's counters into `out` (host).  Thread-safe. */
+int lpd_server_get_stats(lpd_server *server, lpd_server_stats *out);
+
+/* Finishes every submitted request (their completions are then dropped),
+ * stops the worker and frees the server. */
+void lpd_server_destroy(lpd_server *server);
 
 /* Device workspace (bytes) a single solve of an m x n LP allocates. */
 uint64_t lpd_workspace_bytes(int64_t m, int64_t n);

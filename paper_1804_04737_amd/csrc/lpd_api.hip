@@ -100,8 +100,9 @@ int resolve_options(const lpd_problem* prob, const lpd_options* opt, SolveArgs* 
 // paper_1804_04737_amd/autotune.py next to the library, or the file named by
 // LPD_AUTOTUNE_FILE); built-in defaults when there is none.  Read once.
 struct Tuning {
-  int team_size = 16;
-  int64_t team_min_bytes = 4 << 20;
+  int team_size = 0;                    // 0: size teams per LP
+  int64_t team_min_bytes = 2 << 20;
+  int64_t team_bytes_per_wg = 2 << 20;
 };
 
 const Tuning& tuning() {
@@ -134,8 +135,10 @@ const Tuning& tuning() {
       return end == s.c_str() + p + 1 ? dflt : (int64_t)v;
     };
     const int64_t ts = num("team_size", t.team_size);
-    if (ts >= 1 && ts <= 1024) t.team_size = (int)ts;
+    if (ts >= 0 && ts <= 1024) t.team_size = (int)ts;
     t.team_min_bytes = num("team_min_bytes", t.team_min_bytes);
+    const int64_t bw = num("team_bytes_per_wg", t.team_bytes_per_wg);
+    if (bw > 0) t.team_bytes_per_wg = bw;
   });
   return t;
 }
@@ -147,6 +150,15 @@ int hip_err(hipError_t e) {
 }
 
 }  // namespace
+
+BatchKnobs tuned_batch_knobs() {
+  BatchKnobs k;
+  k.team_size = tuning().team_size;
+  k.team_min_bytes = tuning().team_min_bytes;
+  k.team_bytes_per_wg = tuning().team_bytes_per_wg;
+  return k;
+}
+
 }  // namespace lpd
 
 using namespace lpd;
@@ -235,7 +247,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
   if (rc != LPD_SUCCESS) return rc;
 
   double eps_d = LPD_DEFAULT_EPS, eps_p = LPD_DEFAULT_EPS;
-  int64_t max_iter = -1, team_min = 0;
+  int64_t max_iter = -1, team_min = 0, per_wg = 0;
   int team_size = 0, nblocks = dev.ncu;
   int64_t* iterations = nullptr;
   if (opt) {
@@ -245,19 +257,24 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     if (opt->eps_p > 0) eps_p = opt->eps_p;
     max_iter = opt->max_iter;
     if (opt->team_size < 0 || opt->grid_blocks < 0) return LPD_ERR_INVALID_ARG;
+    if (opt->team_bytes_per_wg < 0) return LPD_ERR_INVALID_ARG;
     team_size = opt->team_size;
     team_min = opt->team_min_bytes;
+    per_wg = opt->team_bytes_per_wg;
     if (opt->grid_blocks > 0) nblocks = opt->grid_blocks;
     iterations = opt->iterations;
   }
-  if (team_size == 0) team_size = tuning().team_size;
-  if (team_min == 0) team_min = tuning().team_min_bytes;
+  // Unset knobs (0) come from the autotune table.
+  BatchKnobs knobs;
+  knobs.team_size = team_size > 0 ? team_size : tuning().team_size;
+  knobs.team_min_bytes = team_min != 0 ? team_min : tuning().team_min_bytes;
+  knobs.team_bytes_per_wg = per_wg > 0 ? per_wg : tuning().team_bytes_per_wg;
 
-  BatchPlan P = plan_batch(count, m, n, team_size, team_min, nblocks);
+  BatchPlan P = plan_batch(count, m, n, knobs, nblocks);
   if (!P.ok) return LPD_ERR_TOO_LARGE;
   const int maxb = batch_max_blocks(P.lds_bytes);
   if (maxb <= 0) return LPD_ERR_TOO_LARGE;
-  if (nblocks > maxb) P = plan_batch(count, m, n, team_size, team_min, maxb);
+  if (nblocks > maxb) P = plan_batch(count, m, n, knobs, maxb);
 
   std::vector<BatchItem> items((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
@@ -275,6 +292,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     a.status = status + i;
     a.iterations = iterations ? iterations + i : nullptr;
     items[(size_t)i].klass = P.klass[(size_t)i];
+    items[(size_t)i].tclass = P.tclass[(size_t)i];
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && P.total > total_b) return LPD_ERR_OUT_OF_MEMORY;

@@ -4,17 +4,19 @@
 // (lpd_team.h, lpd_wgsolve.h), so its result is bit-identical to its own
 // lp_solve_dense call.  The launch is cooperative (all workgroups resident):
 //
-//   phase 1  workgroups form teams of S; each team pops the next large LP
-//            (tableau >= team_min_bytes) from a big-first queue and solves it
-//            with the team-scoped reduction barrier;
-//   phase 2  when the large queue is empty, every workgroup pops small LPs
-//            one at a time: LDS-resident if the tableau fits in LDS, else the
-//            one-workgroup grid walk over its private workspace in HBM.
+//   phase 1  the workgroups of team class c form teams of size_c; each team
+//            pops the next LP of its class from a big-first queue and solves
+//            it with the team-scoped reduction barrier (classes group LPs of
+//            similar size: larger LPs get larger teams);
+//   phase 2  when its class queue is empty (or it belongs to no class), a
+//            workgroup pops small LPs one at a time: LDS-resident if the
+//            tableau fits in LDS, else the one-workgroup grid walk over HBM.
 //
 // Queue heads are device-scope atomic counters; a team's pop is broadcast to
 // its members through the team barrier, which also guarantees that every
 // member has finished reading the previous LP before the next one is built in
-// the shared workspace.
+// the shared workspace.  LPs that carry a SolveState may stop after a pivot
+// budget and resume in a later launch (the serving runtime uses this).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -33,28 +35,32 @@ constexpr int kBT = 1024;  // threads per workgroup
 __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int32_t s_idx;
-  const int b = blockIdx.x, S = bw.team_size;
+  const int b = blockIdx.x;
   uint32_t epoch = 0;
 
-  // ---- phase 1: teams on the large LPs
-  const int team = S > 0 ? b / S : 0;
-  if (S > 0 && team < bw.n_teams) {
-    const Team tm{b % S, S, bw.slots + (size_t)team * 2 * S, &epoch};
-    unsigned char* ws = bw.team_ws + (size_t)team * bw.team_ws_stride;
+  // ---- phase 1: teams of this workgroup's class on the large LPs
+  int c = -1;
+  for (int q = 0; q < bw.n_classes; ++q)
+    if (b >= bw.cls[q].base && b < bw.cls[q].base + bw.cls[q].n_teams * bw.cls[q].size) c = q;
+  if (c >= 0) {
+    const TeamClass& tc = bw.cls[c];
+    const int team = (b - tc.base) / tc.size;
+    const Team tm{(b - tc.base) % tc.size, tc.size, tc.slots + (size_t)team * 2 * tc.size, &epoch};
     for (;;) {
-      Cand c = cand_none();
+      Cand pick = cand_none();
       if (tm.rank == 0) {
-        if (threadIdx.x == 0) s_idx = (int32_t)atomicAdd(&bw.counters[0], 1u);
+        if (threadIdx.x == 0) s_idx = (int32_t)atomicAdd(&bw.counters[8 * c], 1u);
         __syncthreads();
-        c.v = 0.0;
-        c.i = s_idx;
+        pick.v = 0.0;
+        pick.i = s_idx;
       }
       // Broadcast the leader's pick; also fences the previous LP of the team.
-      const Cand got = grid_reduce(tm, c, ++epoch, reinterpret_cast<Cand*>(smem));
-      if ((got.flags & kFlagTimeout) || got.i >= bw.n_team) break;
-      const BatchItem& it = bw.items[bw.team_list[__builtin_amdgcn_readfirstlane(got.i)]];
-      const GridLayout L = grid_layout(it.a.m, it.a.n, S);
-      GridWork w = make_grid_work(L, it.a.m, ws);
+      const Cand got = grid_reduce(tm, pick, ++epoch, reinterpret_cast<Cand*>(smem));
+      const int32_t idx = __builtin_amdgcn_readfirstlane(got.i);
+      if ((got.flags & kFlagTimeout) || idx >= tc.n_items) break;
+      const BatchItem& it = bw.items[tc.list[idx]];
+      unsigned char* ws = it.ws ? it.ws : tc.ws + (size_t)team * tc.ws_stride;
+      GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, tc.size), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
       team_solve<kBT, 0>(it.a, w, tm, smem);
@@ -63,10 +69,9 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
 
   // ---- phase 2: one workgroup per small LP
   const Team solo{0, 1, nullptr, &epoch};
-  unsigned char* ws = bw.wg_ws ? bw.wg_ws + (size_t)b * bw.wg_ws_stride : nullptr;
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_idx = (int32_t)atomicAdd(&bw.counters[8], 1u);
+    if (threadIdx.x == 0) s_idx = (int32_t)atomicAdd(&bw.counters[8 * kMaxTeamClasses], 1u);
     __syncthreads();
     const int32_t idx = __builtin_amdgcn_readfirstlane(s_idx);
     if (idx >= bw.n_single) break;
@@ -74,8 +79,8 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
     if (it.klass == kClassLds) {
       wg_solve<kBT>(it.a, smem);
     } else {
-      const GridLayout L = grid_layout(it.a.m, it.a.n, 1);
-      GridWork w = make_grid_work(L, it.a.m, ws);
+      unsigned char* ws = it.ws ? it.ws : bw.wg_ws + (size_t)b * bw.wg_ws_stride;
+      GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, 1), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
       team_solve<kBT, 0>(it.a, w, solo, smem);
@@ -85,7 +90,7 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
 
 __global__ void batch_clear_kernel(uint32_t* counters, BarrierSlot* slots, int nslots) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 2) counters[i * 8] = 0u;
+  if (i <= kMaxTeamClasses) counters[i * 8] = 0u;
   if (i < nslots) slots[i].epoch = 0u;
 }
 
@@ -96,57 +101,143 @@ int lds_limit_bytes() {
   return lds;
 }
 
+int pow2_floor(int64_t x) {
+  int p = 1;
+  while ((int64_t)p * 2 <= x) p *= 2;
+  return p;
+}
+
 }  // namespace
 
-BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, int team_size, int64_t team_min_bytes,
-                     int nblocks) {
+BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const BatchKnobs& K, int nblocks,
+                     size_t lds_per_block) {
   BatchPlan P;
   P.nblocks = nblocks;
   // Static LDS of the kernel (s_idx) plus alignment slack stays outside the dynamic budget.
-  const size_t limit = (size_t)std::max(0, lds_limit_bytes() - 256);
-  std::vector<std::pair<double, int32_t>> team, single;
+  const int lds_total = lds_per_block ? (int)lds_per_block : lds_limit_bytes();
+  const size_t limit = (size_t)std::max(0, lds_total - 256);
+  P.klass.assign((size_t)count, kClassSingle);
+  P.tclass.assign((size_t)count, -1);
+  std::vector<int> want((size_t)count, 0);
+  std::vector<double> work((size_t)count);
+  std::vector<std::pair<double, int32_t>> single;
   int64_t max_vw = 1;
   size_t lds_wg = 0;
+  double w_single = 0.0;
   for (int32_t i = 0; i < count; ++i) {
-    const double R = (double)m[i] + 1, W = (double)(n[i] + m[i] + 1);
-    const double bytes = R * W * 8.0;
-    const double work = bytes * (double)(m[i] + n[i]);  // proxy: tableau size x pivot-count scale
+    const double bytes = tableau_bytes(m[i], n[i]);
+    work[(size_t)i] = bytes * (double)(m[i] + n[i]);  // proxy: tableau size x pivot-count scale
     const size_t lds_i = wg_lds_bytes(m[i], n[i]);
-    int32_t klass;
     if (lds_i <= limit) {
-      klass = kClassLds;
+      P.klass[(size_t)i] = kClassLds;
       lds_wg = std::max(lds_wg, lds_i);
-    } else if (team_size > 1 && team_min_bytes >= 0 && bytes >= (double)team_min_bytes) {
-      klass = kClassTeam;
     } else {
-      klass = kClassSingle;
+      max_vw = std::max<int64_t>(max_vw, (n[i] + m[i] + 1) / 2);
+      if (K.team_min_bytes >= 0 && bytes >= (double)K.team_min_bytes) {
+        int s = 0;
+        if (K.team_size > 0) s = K.team_size;
+        else if (K.team_bytes_per_wg > 0) s = pow2_floor((int64_t)(bytes / (double)K.team_bytes_per_wg));
+        s = std::min(s, nblocks);
+        if (s >= 2) {
+          P.klass[(size_t)i] = kClassTeam;
+          want[(size_t)i] = s;
+        }
+      }
     }
-    P.klass.push_back(klass);
-    if (klass != kClassLds) max_vw = std::max<int64_t>(max_vw, (n[i] + m[i] + 1) / 2);
-    (klass == kClassTeam ? team : single).push_back({-work, i});
+    if (P.klass[(size_t)i] != kClassTeam) {
+      single.push_back({-work[(size_t)i], i});
+      w_single += work[(size_t)i];
+    }
   }
-  std::stable_sort(team.begin(), team.end());
+  // Team classes: the distinct wanted sizes, largest first; beyond
+  // kMaxTeamClasses the smaller sizes join the smallest kept class.
+  std::vector<int> sizes;
+  for (int s : want)
+    if (s >= 2 && std::find(sizes.begin(), sizes.end(), s) == sizes.end()) sizes.push_back(s);
+  std::sort(sizes.rbegin(), sizes.rend());
+  // At most kMaxTeamClasses classes, and few enough that every class keeps a
+  // team of two or more when the grid is small (the shrink loop below ends).
+  const int max_classes = std::min(kMaxTeamClasses, nblocks / 2);
+  if ((int)sizes.size() > max_classes) sizes.resize((size_t)std::max(0, max_classes));
+  if (sizes.empty())
+    for (int32_t i = 0; i < count; ++i)
+      if (P.klass[(size_t)i] == kClassTeam) {
+        P.klass[(size_t)i] = kClassSingle;
+        single.push_back({-work[(size_t)i], i});
+        w_single += work[(size_t)i];
+      }
+  P.n_classes = (int)sizes.size();
+  std::vector<std::pair<double, int32_t>> cl[kMaxTeamClasses];
+  double wc[kMaxTeamClasses] = {};
+  for (int32_t i = 0; i < count; ++i) {
+    if (P.klass[(size_t)i] != kClassTeam) continue;
+    int c = P.n_classes - 1;
+    for (int q = 0; q < P.n_classes; ++q)
+      if (sizes[(size_t)q] == want[(size_t)i]) c = q;
+    P.tclass[(size_t)i] = c;
+    cl[c].push_back({-work[(size_t)i], i});
+    wc[c] += work[(size_t)i];
+  }
+  double w_all = w_single;
+  for (int c = 0; c < P.n_classes; ++c) w_all += wc[c];
+  // Workgroups per class in proportion to its work (at least one team, at
+  // most one team per LP); the rest starts on the one-workgroup queue.
+  int used = 0;
+  for (int c = 0; c < P.n_classes; ++c) {
+    int s = sizes[(size_t)c];
+    int g = (int)(nblocks * (wc[c] / std::max(w_all, 1.0)));
+    g = std::max(s, g / s * s);
+    g = std::min<int>(g, (int)cl[c].size() * s);
+    P.cls_size[c] = s;
+    P.cls_teams[c] = g / s;
+    used += g;
+  }
+  while (used > nblocks) {  // shrink the class with the most workgroups
+    int big = 0;
+    for (int c = 1; c < P.n_classes; ++c)
+      if (P.cls_teams[c] * P.cls_size[c] > P.cls_teams[big] * P.cls_size[big]) big = c;
+    if (P.cls_teams[big] > 1) {
+      --P.cls_teams[big];
+      used -= P.cls_size[big];
+    } else if (P.cls_size[big] > 2) {
+      used -= P.cls_size[big] / 2;
+      P.cls_size[big] /= 2;
+    } else {
+      break;  // every class is down to one team of two: n_classes * 2 <= nblocks
+    }
+  }
+  int base = 0;
+  for (int c = 0; c < P.n_classes; ++c) {
+    P.cls_base[c] = base;
+    base += P.cls_teams[c] * P.cls_size[c];
+    std::stable_sort(cl[c].begin(), cl[c].end());
+    for (auto& e : cl[c]) P.cls_list[c].push_back(e.second);
+  }
   std::stable_sort(single.begin(), single.end());
-  for (auto& t : team) P.team_list.push_back(t.second);
-  for (auto& s : single) P.single_list.push_back(s.second);
-  P.team_size = team.empty() ? 0 : std::max(1, std::min(team_size, nblocks));
-  P.n_teams = P.team_size ? nblocks / P.team_size : 0;
+  for (auto& e : single) P.single_list.push_back(e.second);
 
   // LDS: the grid walk needs the pivot row of the widest non-LDS LP plus a
   // capture list; the LDS-resident LPs need their whole tableau.
-  const size_t base = kScratchBytes + (size_t)max_vw * 16 + 16;
-  P.ok = base <= limit;
+  const size_t lbase = kScratchBytes + (size_t)max_vw * 16 + 16;
+  P.ok = lbase <= limit;
   P.lds_vecs = (int32_t)max_vw;
-  P.cap_cap = P.ok ? (int32_t)std::min<size_t>(kCapMax, (limit - base) / kCapEntryBytes) : 0;
-  P.lds_bytes = std::max(lds_wg, base + (size_t)P.cap_cap * kCapEntryBytes);
+  P.cap_cap = P.ok ? (int32_t)std::min<size_t>(kCapMax, (limit - lbase) / kCapEntryBytes) : 0;
+  P.lds_bytes = std::max(lds_wg, lbase + (size_t)P.cap_cap * kCapEntryBytes);
 
-  // Workspaces: one per team (largest team LP), one per workgroup (largest single LP in HBM).
-  uint64_t team_ws = 0, wg_ws = 0;
-  for (int32_t i : P.team_list) team_ws = std::max<uint64_t>(team_ws, grid_layout(m[i], n[i], P.team_size).total);
-  for (int32_t i : P.single_list)
-    if (P.klass[i] == kClassSingle) wg_ws = std::max<uint64_t>(wg_ws, grid_layout(m[i], n[i], 1).total);
-  P.team_ws_stride = team_ws;
-  P.wg_ws_stride = wg_ws;
+  // Shared workspaces unless every LP brings its own.
+  uint64_t team_ws_total = 0, nslots = 0;
+  for (int c = 0; c < P.n_classes; ++c) {
+    uint64_t s = 0;
+    if (!K.own_workspaces)
+      for (int32_t i : P.cls_list[c]) s = std::max<uint64_t>(s, grid_layout(m[i], n[i], 1).total);
+    P.cls_ws_stride[c] = s;
+    team_ws_total += (uint64_t)P.cls_teams[c] * s;
+    nslots += (uint64_t)P.cls_teams[c] * 2 * P.cls_size[c];
+  }
+  if (!K.own_workspaces)
+    for (int32_t i : P.single_list)
+      if (P.klass[(size_t)i] == kClassSingle)
+        P.wg_ws_stride = std::max<uint64_t>(P.wg_ws_stride, grid_layout(m[i], n[i], 1).total);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
@@ -154,11 +245,11 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, int team
     return o;
   };
   P.off_items = take((uint64_t)count * sizeof(BatchItem));
-  P.off_lists = take((uint64_t)(P.team_list.size() + P.single_list.size()) * 4 + 4);
-  P.off_counters = take(64);
-  P.off_slots = take((uint64_t)P.n_teams * 2 * std::max(P.team_size, 1) * sizeof(BarrierSlot));
-  P.off_team_ws = take((uint64_t)P.n_teams * team_ws);
-  P.off_wg_ws = take((uint64_t)nblocks * wg_ws);
+  P.off_lists = take((uint64_t)count * 4 + 4);
+  P.off_counters = take(32 * (kMaxTeamClasses + 1) + 32);
+  P.off_slots = take(nslots * sizeof(BarrierSlot));
+  P.off_team_ws = take(team_ws_total);
+  P.off_wg_ws = take((uint64_t)nblocks * P.wg_ws_stride);
   P.total = off;
   return P;
 }
@@ -171,30 +262,42 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
   std::vector<unsigned char> host(P.off_counters);
   std::memcpy(host.data() + P.off_items, items.data(), items.size() * sizeof(BatchItem));
   int32_t* lists = reinterpret_cast<int32_t*>(host.data() + P.off_lists);
-  std::copy(P.team_list.begin(), P.team_list.end(), lists);
-  std::copy(P.single_list.begin(), P.single_list.end(), lists + P.team_list.size());
+  BatchWork bw{};
+  bw.items = reinterpret_cast<const BatchItem*>(base + P.off_items);
+  const int32_t* dlists = reinterpret_cast<const int32_t*>(base + P.off_lists);
+  size_t at = 0;
+  BarrierSlot* slots = reinterpret_cast<BarrierSlot*>(base + P.off_slots);
+  unsigned char* tws = base + P.off_team_ws;
+  bw.n_classes = P.n_classes;
+  for (int c = 0; c < P.n_classes; ++c) {
+    TeamClass& tc = bw.cls[c];
+    tc.size = P.cls_size[c];
+    tc.base = P.cls_base[c];
+    tc.n_teams = P.cls_teams[c];
+    tc.n_items = (int32_t)P.cls_list[c].size();
+    std::copy(P.cls_list[c].begin(), P.cls_list[c].end(), lists + at);
+    tc.list = dlists + at;
+    at += P.cls_list[c].size();
+    tc.ws = P.cls_ws_stride[c] ? tws : nullptr;
+    tc.ws_stride = P.cls_ws_stride[c];
+    tws += (size_t)tc.n_teams * tc.ws_stride;
+    tc.slots = slots;
+    slots += (size_t)tc.n_teams * 2 * tc.size;
+  }
+  std::copy(P.single_list.begin(), P.single_list.end(), lists + at);
+  bw.single_list = dlists + at;
+  bw.n_single = (int32_t)P.single_list.size();
+  bw.counters = reinterpret_cast<uint32_t*>(base + P.off_counters);
+  bw.wg_ws = P.wg_ws_stride ? base + P.off_wg_ws : nullptr;
+  bw.wg_ws_stride = P.wg_ws_stride;
+  bw.cap_cap = P.cap_cap;
+  bw.lds_vecs = P.lds_vecs;
   hipError_t e = hipMemcpyAsync(base, host.data(), host.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return e;
 
-  BatchWork bw{};
-  bw.items = reinterpret_cast<const BatchItem*>(base + P.off_items);
-  bw.team_list = reinterpret_cast<const int32_t*>(base + P.off_lists);
-  bw.n_team = (int32_t)P.team_list.size();
-  bw.single_list = bw.team_list + P.team_list.size();
-  bw.n_single = (int32_t)P.single_list.size();
-  bw.counters = reinterpret_cast<uint32_t*>(base + P.off_counters);
-  bw.slots = reinterpret_cast<BarrierSlot*>(base + P.off_slots);
-  bw.team_ws = base + P.off_team_ws;
-  bw.team_ws_stride = P.team_ws_stride;
-  bw.wg_ws = P.wg_ws_stride ? base + P.off_wg_ws : nullptr;
-  bw.wg_ws_stride = P.wg_ws_stride;
-  bw.team_size = P.team_size;
-  bw.n_teams = P.n_teams;
-  bw.cap_cap = P.cap_cap;
-  bw.lds_vecs = P.lds_vecs;
-
-  const int nslots = P.n_teams * 2 * std::max(P.team_size, 1);
-  batch_clear_kernel<<<(std::max(nslots, 2) + 255) / 256, 256, 0, stream>>>(bw.counters, bw.slots, nslots);
+  const int nslots = (int)(slots - reinterpret_cast<BarrierSlot*>(base + P.off_slots));
+  batch_clear_kernel<<<(std::max(nslots, kMaxTeamClasses + 1) + 255) / 256, 256, 0, stream>>>(
+      bw.counters, reinterpret_cast<BarrierSlot*>(base + P.off_slots), nslots);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);

@@ -7,6 +7,14 @@
 
 namespace lpd {
 
+// Where a resumable solve stands between launches (device memory, one per LP).
+struct SolveState {
+  int32_t phase;   // 0: not started, 1: suspended between pivots, 2: finished
+  int32_t k, l, lprev;
+  double g, p;
+  int64_t iter;
+};
+
 // Inputs, options and outputs of one LP solve as the kernels see them.
 struct SolveArgs {
   int64_t m, n;
@@ -27,6 +35,11 @@ struct SolveArgs {
   double* tableau_out;
   uint64_t* phase_ticks;
   int64_t phase_cap;
+  // Resumable solves (grid walk only): state kept in device memory between
+  // launches, and the most pivots one launch may do (< 0: no limit).  The
+  // budget is ignored when state is null.
+  SolveState* state;
+  int64_t pivot_budget;
 };
 
 // Reduction-barrier slot: one per workgroup and per epoch parity, 128 B apart.

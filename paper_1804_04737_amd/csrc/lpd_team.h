@@ -187,96 +187,112 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const int32_t pub_v1 = (int32_t)((int64_t)vw * (tm.rank + 1) / nb);
   uint32_t& epoch = *tm.epoch;
 
-  // ---------------- Step 1: initial tableau (Table 1) ----------------
-  int32_t flags = 0;
-  {
-    int32_t i = i_start, v = v_start;
-    while (i < m) {
-      const int32_t j0 = 2 * v, j1 = 2 * v + 1;
-      const double* Ai = a.A + (int64_t)i * n;
-      dbl2 t;
-      t.x = j0 < n ? Ai[j0] : (j0 == n + i ? 1.0 : 0.0);
-      t.y = j1 < n ? Ai[j1] : (j1 == n + i ? 1.0 : 0.0);
-      if (!is_finite(t.x) || !is_finite(t.y)) flags |= kFlagNonFinite;
-      st_stream(reinterpret_cast<dbl2*>(w.T + (int64_t)i * ld) + v, t);
-      v += step_r;
-      i += step_q;
-      if (v >= vw) { v -= vw; ++i; }
-    }
-  }
-  for (int64_t v = gid; v < vw; v += G) {
-    const int64_t j0 = 2 * v, j1 = 2 * v + 1;
-    dbl2 o;
-    o.x = j0 < n ? -a.c[j0] : 0.0;
-    o.y = j1 < n ? -a.c[j1] : 0.0;
-    if (!is_finite(o.x) || !is_finite(o.y)) flags |= kFlagNonFinite;
-    reinterpret_cast<dbl2*>(w.obj[0])[v] = o;
-  }
-  for (int64_t i = gid; i <= m; i += G) {
-    double bi = 0.0;
-    if (i < m) {
-      bi = a.b[i];
-      if (!is_finite(bi)) flags |= kFlagNonFinite;
-      if (bi < 0.0) flags |= kFlagNegativeB;
-      w.basis[i] = (int32_t)(n + i);
-    }
-    w.rhs[0][i] = bi;
-  }
-  for (int64_t j = gid; j < ncols; j += G) w.pos[j] = j < n ? -1 : (int32_t)(j - n);
-
   int32_t status = -1;
   int64_t iter = 0;
   int32_t lprev = -1;  // pivot row of the last pivot done (-1: none)
   int32_t fpar = 0;    // parity of the current objective / rhs buffers
-  {
-    Cand f0 = cand_none();
-    f0.flags = flags;
-    f0 = block_reduce(f0, scratch);
-    const Cand gf = grid_reduce(tm, f0, ++epoch, scratch);
-    if (gf.flags & kFlagTimeout) status = kDeviceTimeout;
-    else if (gf.flags & kFlagNonFinite) status = kNumerical;
-    else if (gf.flags & kFlagNegativeB) status = kInfeasibleStart;
-  }
-
-  // ---------------- Step 2 on the initial objective row ----------------
   int32_t k = -1, l = -1;
   double g = 0.0, p = 1.0;
-  if (status < 0) {
-    Cand pc = cand_none();
-    const dbl2* o = reinterpret_cast<const dbl2*>(w.obj[0]);
-    for (int32_t v = tid; v < vw; v += NT) {
-      const dbl2 ov = o[v];
-      price_offer(pc, ov.x, 2 * (int64_t)v, ncols);
-      price_offer(pc, ov.y, 2 * (int64_t)v + 1, ncols);
+  // A resumable solve that was suspended between pivots picks up where it
+  // stopped: the tableau and vectors are in the workspace, the scalars here.
+  const bool resume = a.state != nullptr && a.state->phase == 1;
+  if (resume) {
+    k = a.state->k;
+    l = a.state->l;
+    lprev = a.state->lprev;
+    g = a.state->g;
+    p = a.state->p;
+    iter = a.state->iter;
+    fpar = (int32_t)(iter & 1);
+  } else {
+    // ---------------- Step 1: initial tableau (Table 1) ----------------
+    int32_t flags = 0;
+    {
+      int32_t i = i_start, v = v_start;
+      while (i < m) {
+        const int32_t j0 = 2 * v, j1 = 2 * v + 1;
+        const double* Ai = a.A + (int64_t)i * n;
+        dbl2 t;
+        t.x = j0 < n ? Ai[j0] : (j0 == n + i ? 1.0 : 0.0);
+        t.y = j1 < n ? Ai[j1] : (j1 == n + i ? 1.0 : 0.0);
+        if (!is_finite(t.x) || !is_finite(t.y)) flags |= kFlagNonFinite;
+        st_stream(reinterpret_cast<dbl2*>(w.T + (int64_t)i * ld) + v, t);
+        v += step_r;
+        i += step_q;
+        if (v >= vw) { v -= vw; ++i; }
+      }
     }
-    pc = block_reduce(pc, scratch);
-    if (pc.flags & kFlagNonFinite) status = kNumerical;
-    else if (pc.v >= -a.eps_d) status = kOptimal;
-    else if (a.max_iter == 0) status = kIterLimit;
-    k = pc.i;
-    g = pc.v;
-  }
-  // ---------------- Step 3 on the initial tableau ----------------
-  if (status < 0) {
-    Cand rc = cand_none();
-    for (int64_t i = gid; i < m; i += G) {
-      const double aik = w.T[i * ld + k];
-      const double r = w.rhs[0][i];
-      w.pcol[0][i] = aik;
-      ratio_offer(rc, aik, r, (int32_t)i, a.eps_p);
+    for (int64_t v = gid; v < vw; v += G) {
+      const int64_t j0 = 2 * v, j1 = 2 * v + 1;
+      dbl2 o;
+      o.x = j0 < n ? -a.c[j0] : 0.0;
+      o.y = j1 < n ? -a.c[j1] : 0.0;
+      if (!is_finite(o.x) || !is_finite(o.y)) flags |= kFlagNonFinite;
+      reinterpret_cast<dbl2*>(w.obj[0])[v] = o;
     }
-    rc = block_reduce(rc, scratch);
-    const Cand gr = grid_reduce(tm, rc, ++epoch, scratch);
-    if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
-    else if (gr.flags & kFlagNonFinite) status = kNumerical;
-    else if (gr.i == kNoIndex) status = kUnbounded;
-    l = gr.i;
-    p = gr.aux;
+    for (int64_t i = gid; i <= m; i += G) {
+      double bi = 0.0;
+      if (i < m) {
+        bi = a.b[i];
+        if (!is_finite(bi)) flags |= kFlagNonFinite;
+        if (bi < 0.0) flags |= kFlagNegativeB;
+        w.basis[i] = (int32_t)(n + i);
+      }
+      w.rhs[0][i] = bi;
+    }
+    for (int64_t j = gid; j < ncols; j += G) w.pos[j] = j < n ? -1 : (int32_t)(j - n);
+
+    {
+      Cand f0 = cand_none();
+      f0.flags = flags;
+      f0 = block_reduce(f0, scratch);
+      const Cand gf = grid_reduce(tm, f0, ++epoch, scratch);
+      if (gf.flags & kFlagTimeout) status = kDeviceTimeout;
+      else if (gf.flags & kFlagNonFinite) status = kNumerical;
+      else if (gf.flags & kFlagNegativeB) status = kInfeasibleStart;
+    }
+
+    // ---------------- Step 2 on the initial objective row ----------------
+    if (status < 0) {
+      Cand pc = cand_none();
+      const dbl2* o = reinterpret_cast<const dbl2*>(w.obj[0]);
+      for (int32_t v = tid; v < vw; v += NT) {
+        const dbl2 ov = o[v];
+        price_offer(pc, ov.x, 2 * (int64_t)v, ncols);
+        price_offer(pc, ov.y, 2 * (int64_t)v + 1, ncols);
+      }
+      pc = block_reduce(pc, scratch);
+      if (pc.flags & kFlagNonFinite) status = kNumerical;
+      else if (pc.v >= -a.eps_d) status = kOptimal;
+      else if (a.max_iter == 0) status = kIterLimit;
+      k = pc.i;
+      g = pc.v;
+    }
+    // ---------------- Step 3 on the initial tableau ----------------
+    if (status < 0) {
+      Cand rc = cand_none();
+      for (int64_t i = gid; i < m; i += G) {
+        const double aik = w.T[i * ld + k];
+        const double r = w.rhs[0][i];
+        w.pcol[0][i] = aik;
+        ratio_offer(rc, aik, r, (int32_t)i, a.eps_p);
+      }
+      rc = block_reduce(rc, scratch);
+      const Cand gr = grid_reduce(tm, rc, ++epoch, scratch);
+      if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
+      else if (gr.flags & kFlagNonFinite) status = kNumerical;
+      else if (gr.i == kNoIndex) status = kUnbounded;
+      l = gr.i;
+      p = gr.aux;
+    }
   }
 
   // ---------------- pivot loop ----------------
   const bool ticks = leader && a.phase_ticks != nullptr;
+  int64_t done_here = 0;  // pivots done by this call
   while (status < 0) {
+    if (a.state && a.pivot_budget >= 0 && done_here == a.pivot_budget) break;  // suspend
+    ++done_here;
     uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
     if (tk && tid == 0) tk[0] = __builtin_amdgcn_s_memrealtime();
     const int cur = (int)(iter & 1), nxt = cur ^ 1;
@@ -422,6 +438,21 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     l = gr.i;
     p = gr.aux;
   }
+
+  if (status < 0) {
+    // Suspended: keep the scalars for the next call (all workgroups agree).
+    if (leader && tid == 0) {
+      a.state->phase = 1;
+      a.state->k = k;
+      a.state->l = l;
+      a.state->lprev = lprev;
+      a.state->g = g;
+      a.state->p = p;
+      a.state->iter = iter;
+    }
+    return;
+  }
+  if (a.state && leader && tid == 0) a.state->phase = 2;
 
   // ---------------- solution read-out ----------------
   const double* rhs_f = w.rhs[fpar];

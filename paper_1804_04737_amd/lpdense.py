@@ -20,8 +20,9 @@ STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "
 SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID = 0, 1, 2
 
 # Exported symbols, as declared in include/lpdense.h.
-EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lpd_workspace_bytes",
-           "lpd_error_string", "lpd_status_string", "lpd_version")
+EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lpd_server_create",
+           "lpd_server_submit", "lpd_server_poll", "lpd_server_get_stats", "lpd_server_destroy",
+           "lpd_workspace_bytes", "lpd_error_string", "lpd_status_string", "lpd_version")
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -45,7 +46,26 @@ class Outputs(ctypes.Structure):
 class BatchOptions(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
                 ("team_size", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("team_min_bytes", _I64), ("iterations", _P)]
+                ("team_min_bytes", _I64), ("iterations", _P), ("team_bytes_per_wg", _I64)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
+                ("pivots_per_epoch", _I64), ("max_resident", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("team_min_bytes", _I64), ("team_bytes_per_wg", _I64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", _I64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("obj", ctypes.c_double), ("iterations", _I64), ("m", _I64), ("n", _I64),
+                ("x", _P), ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _I64), ("completed", _I64), ("epochs", _I64), ("resident", _I64),
+                ("waiting", _I64), ("used_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64)]
 
 
 class LpdError(RuntimeError):
@@ -73,6 +93,16 @@ def load(path: str = LIB_PATH):
     lib.lp_solve_batch.restype = ctypes.c_int
     lib.lp_solve_batch.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                    ctypes.POINTER(BatchOptions), _P]
+    lib.lpd_server_create.restype = _P
+    lib.lpd_server_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ServerOptions)]
+    lib.lpd_server_submit.restype = _I64
+    lib.lpd_server_submit.argtypes = [_P, _I64, _I64, _P, _P, _P, _P]
+    lib.lpd_server_poll.restype = ctypes.c_int
+    lib.lpd_server_poll.argtypes = [_P, ctypes.POINTER(Completion), ctypes.c_int]
+    lib.lpd_server_get_stats.restype = ctypes.c_int
+    lib.lpd_server_get_stats.argtypes = [_P, ctypes.POINTER(ServerStats)]
+    lib.lpd_server_destroy.restype = None
+    lib.lpd_server_destroy.argtypes = [_P]
     lib.lpd_workspace_bytes.restype = ctypes.c_uint64
     lib.lpd_workspace_bytes.argtypes = [_I64, _I64]
     lib.lpd_error_string.restype = ctypes.c_char_p
@@ -241,13 +271,14 @@ def pack_batch(lps, device="cuda") -> PackedBatch:
 
 
 def solve_batch(pb: PackedBatch, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
-                team_size: int = 0, team_min_bytes: int = 0, grid_blocks: int = 0, stream=None) -> PackedBatch:
+                team_size: int = 0, team_min_bytes: int = 0, team_bytes_per_wg: int = 0,
+                grid_blocks: int = 0, stream=None) -> PackedBatch:
     """lp_solve_batch on a PackedBatch (asynchronous; outputs land in pb)."""
     import numpy as np
     def hp(a):
         return a.ctypes.data_as(ctypes.c_void_p)
     opts = BatchOptions(float(eps_d), float(eps_p), int(max_iter), int(team_size), int(grid_blocks),
-                        int(team_min_bytes), pb.iterations.data_ptr())
+                        int(team_min_bytes), pb.iterations.data_ptr(), int(team_bytes_per_wg))
     m = np.ascontiguousarray(pb.m, dtype=np.int64)
     n = np.ascontiguousarray(pb.n, dtype=np.int64)
     rc = load().lp_solve_batch(pb.count, hp(m), hp(n), pb.A.data_ptr(), hp(pb.A_off), pb.b.data_ptr(),
@@ -257,3 +288,101 @@ def solve_batch(pb: PackedBatch, *, eps_d: float = 0.0, eps_p: float = 0.0, max_
     if rc != 0:
         raise LpdError(rc, "lp_solve_batch")
     return pb
+
+
+@dataclass
+class Served:
+    """One finished request of a Server."""
+    id: int
+    status: int
+    obj: float
+    iterations: int
+    x: "object"          # numpy float64 array (n)
+    t_arrive: float      # seconds since the server started
+    t_admit: float
+    t_done: float
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrive
+
+
+class Server:
+    """lpd_server_* : continuous batching of LPs submitted from the host.
+
+    submit() takes host numpy arrays (kept alive here until the request
+    completes) and returns the request id; poll() returns the requests that
+    finished since the last call."""
+
+    def __init__(self, budget_bytes: int, *, device: int = 0, pivots_per_epoch: int = 0,
+                 max_resident: int = 0, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = 0,
+                 team_min_bytes: int = 0, team_bytes_per_wg: int = 0):
+        opts = ServerOptions(float(eps_d), float(eps_p), int(max_iter), int(pivots_per_epoch),
+                             int(max_resident), 0, int(team_min_bytes), int(team_bytes_per_wg))
+        self._lib = load()
+        h = self._lib.lpd_server_create(int(device), int(budget_bytes), ctypes.byref(opts))
+        if not h:
+            raise RuntimeError("lpd_server_create failed (no usable gfx950 device or out of memory)")
+        self._h = ctypes.c_void_p(h)
+        self._live = {}
+        self._buf = (Completion * 256)()
+
+    def submit(self, A, b, c) -> int:
+        import numpy as np
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        m, n = A.shape
+        if b.shape != (m,) or c.shape != (n,):
+            raise ValueError("b must have m entries and c n entries")
+        x = np.empty(n, dtype=np.float64)
+        def hp(a):
+            return a.ctypes.data_as(ctypes.c_void_p)
+        rid = int(self._lib.lpd_server_submit(self._h, m, n, hp(A), hp(b), hp(c), hp(x)))
+        if rid < 0:
+            raise LpdError(rid, "lpd_server_submit")
+        self._live[rid] = (A, b, c, x)
+        return rid
+
+    def poll(self):
+        out = []
+        while True:
+            k = self._lib.lpd_server_poll(self._h, self._buf, len(self._buf))
+            if k < 0:
+                raise LpdError(k, "lpd_server_poll")
+            for i in range(k):
+                cp = self._buf[i]
+                _, _, _, x = self._live.pop(int(cp.id))
+                out.append(Served(int(cp.id), int(cp.status), float(cp.obj), int(cp.iterations), x,
+                                  float(cp.t_arrive), float(cp.t_admit), float(cp.t_done)))
+            if k < len(self._buf):
+                return out
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        rc = self._lib.lpd_server_get_stats(self._h, ctypes.byref(st))
+        if rc != 0:
+            raise LpdError(rc, "lpd_server_get_stats")
+        return st
+
+    @property
+    def outstanding(self) -> int:
+        return len(self._live)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lpd_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -74,3 +74,50 @@ def test_batch_host_validation_without_device():
     assert f(1, p(zero), p(one), d, p(zero), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -1
     assert f(1, p(one), p(one), None, p(zero), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -2
     assert f(1, p(one), p(one), d, p(neg), d, p(zero), d, p(zero), d, p(zero), d, d, None, None) == -1
+
+
+def test_server_host_validation_without_device():
+    lib = lpdense.load()
+    d = ctypes.c_void_p(0x1000)
+    assert lib.lpd_server_submit(None, 3, 3, d, d, d, d) == -8
+    assert lib.lpd_server_poll(None, None, 0) == -1
+    assert lib.lpd_server_get_stats(None, None) == -2
+    lib.lpd_server_destroy(None)
+
+
+def _c_layout(structs):
+    """sizeof and field offsets of header structs, from a C compiler."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lpdense.h"', "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        r = subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", f"-I{os.path.dirname(HEADER)}",
+                            "-I/opt/rocm/include", src, "-o", exe], capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("header does not compile with the host C compiler: " + r.stderr[-300:])
+        return [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+
+
+def test_python_struct_mirrors_match_the_header():
+    mirrors = [("lpd_problem", lpdense.Problem), ("lpd_options", lpdense.Options),
+               ("lpd_outputs", lpdense.Outputs), ("lpd_batch_options", lpdense.BatchOptions),
+               ("lpd_server_options", lpdense.ServerOptions), ("lpd_completion", lpdense.Completion),
+               ("lpd_server_stats", lpdense.ServerStats)]
+    structs = [(cname, [f for f, _ in py._fields_]) for cname, py in mirrors]
+    got = _c_layout(structs)
+    want = []
+    for _, py in mirrors:
+        want.append(ctypes.sizeof(py))
+        want += [getattr(py, f).offset for f, _ in py._fields_]
+    assert got == want
