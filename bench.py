@@ -136,8 +136,103 @@ def batch_bench(args):
                    "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / args.steps), 1),
                    "effective_GBps": round(bytes_step / (el / args.steps) / 1e9, 1),
                    "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
+                   "one_at_a_time_effective_GBps": round(b1 / el1 / 1e9, 1),
                    "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
                    "team_size": args.team_size, "team_min_bytes": args.team_min_bytes},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Served workload: Poisson arrivals of dense LPs (m, n log-uniform in
+    [64, 4096], seed-fixed pool) submitted from the host to one lpd_server
+    with a footprint budget; per arrival rate, p50/p99 latency (submit to
+    result in host memory) and completed LPs/s.  Compared with solving the
+    same requests one lp_solve_dense_ex call at a time (host copies included,
+    as for the server)."""
+    import numpy as np
+    import torch
+
+    from paper_1804_04737_amd import lpdense, lpgen
+    lpdense.load()
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    # Requests live in pinned host memory, as a serving front end would keep them.
+    keep = []
+    def pinned(a):
+        t = torch.from_numpy(a).pin_memory()
+        keep.append(t)
+        return t.numpy()
+    pool = [tuple(pinned(v) for v in lp) for lp in lpgen.batch_lps(args.serve_pool, 64, 4096, args.seed)]
+    log(f"pool of {len(pool)} LPs generated (pinned host memory)")
+    rng = np.random.default_rng(args.seed + 1)
+    picks = [int(v) for v in rng.integers(0, len(pool), size=args.serve_requests)]
+    dev = torch.device("cuda")
+
+    # One at a time: host inputs copied in, solved, x copied back, per request.
+    stream = torch.cuda.current_stream()
+    def one(lp):
+        A, b, c = (torch.from_numpy(v).to(dev, non_blocking=False) for v in lp)
+        r = lpdense.solve_dense_ex(A, b, c, want_y=False, stream=stream)
+        return r.x.cpu(), int(r.iterations.item())
+    def alg_bytes(m, n, piv):
+        return 16.0 * (m + 1) * (n + m + 1) * piv
+    for q in range(min(3, len(pool))):
+        one(pool[picks[q]])
+    torch.cuda.synchronize()
+    n1 = min(len(picks), args.serve_single)
+    t0 = time.perf_counter()
+    b1 = 0.0
+    for q in range(n1):
+        _, piv = one(pool[picks[q]])
+        b1 += alg_bytes(*pool[picks[q]][0].shape, piv)
+    torch.cuda.synchronize()
+    el1 = max(time.perf_counter() - t0, 1e-9)
+    single_lps_s = n1 / el1 if n1 else float("nan")
+    log(f"one at a time: {single_lps_s:.1f} LPs/s over {n1} requests, {b1 / el1 / 1e9:.0f} GB/s effective")
+
+    sweep = []
+    for rate in rates:
+        arr = lpgen.poisson_arrivals(rate, len(picks), args.seed + int(rate))
+        with lpdense.Server(int(args.budget_gb * 1e9), pivots_per_epoch=args.pivots_per_epoch,
+                            epoch_bytes_per_wg=int(args.epoch_mb * (1 << 20)),
+                            team_bytes_per_wg=int(args.share_kb * 1024)) as srv:
+            done = []
+            i = 0
+            t0 = time.perf_counter()
+            while len(done) < len(picks):
+                now = time.perf_counter() - t0
+                while i < len(picks) and arr[i] <= now:
+                    srv.submit(*pool[picks[i]])
+                    i += 1
+                done += srv.poll()
+                wait = (arr[i] - (time.perf_counter() - t0)) if i < len(picks) else 0.0005
+                time.sleep(min(max(wait, 0.0), 0.0005))
+            st = srv.stats()
+        bad = [d for d in done if d.status != lpdense.OPTIMAL]
+        lat = np.array([d.latency for d in done]) * 1e3
+        span = max(d.t_done for d in done) - min(d.t_arrive for d in done)
+        gb = sum(alg_bytes(d.m, d.n, d.iterations) for d in done) / 1e9
+        row = {"rate_per_s": rate, "requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+               "p99_ms": round(float(np.percentile(lat, 99)), 2), "LPs_per_s": round(len(done) / span, 1),
+               "effective_GBps": round(gb / span, 1), "kernel_busy": round(st.kernel_seconds / span, 3),
+               "admit_host_s": round(st.admit_host_seconds, 3),
+               "epochs": int(st.epochs), "peak_GB": round(st.peak_bytes / 1e9, 2), "not_optimal": len(bad)}
+        log(f"rate {rate:g}/s: {row}")
+        sweep.append(row)
+    top = sweep[-1]
+    out = {
+        "metric": METRIC, "value": top["LPs_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": len(rates),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"served: Poisson arrivals of {len(picks)} dense LPs per rate drawn from a pool of "
+                               f"{len(pool)} (m, n log-uniform in [64, 4096], seed {args.seed}), footprint budget "
+                               f"{args.budget_gb:g} GB, " + (f"{args.pivots_per_epoch} pivots per LP per epoch" if args.pivots_per_epoch > 0
+                                 else f"pivot budgets sized for {args.epoch_mb:g} MiB per workgroup per epoch"),
+                   "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
+                   "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
+                   "one_at_a_time_effective_GBps": round(b1 / el1 / 1e9, 1),
+                   "speedup_vs_one_at_a_time": round(top["LPs_per_s"] / single_lps_s, 2) if n1 else None,
+                   "sweep": sweep},
     }
     print(json.dumps(out), flush=True)
 
@@ -158,7 +253,18 @@ def main():
                     help="after the timed steps, run one more solve with per-phase device timestamps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
-    ap.add_argument("--workload", choices=["dense", "batch"], default="dense")
+    ap.add_argument("--workload", choices=["dense", "batch", "serve"], default="dense")
+    ap.add_argument("--serve-rates", default="100,1000,5000", help="serve: arrival rates (LPs/s)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="serve: requests per rate")
+    ap.add_argument("--serve-pool", type=int, default=48, help="serve: distinct LPs the requests draw from")
+    ap.add_argument("--serve-single", type=int, default=100, help="serve: requests timed one at a time")
+    ap.add_argument("--pivots-per-epoch", type=int, default=0,
+                    help="serve: pivot budget per LP per launch (0: sized per LP from --epoch-mb)")
+    ap.add_argument("--epoch-mb", type=float, default=256.0,
+                    help="serve: tableau MiB each workgroup streams per launch (sizes the pivot budgets)")
+    ap.add_argument("--share-kb", type=float, default=0,
+                    help="serve: least tableau KiB per workgroup of a team (0: library default)")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: footprint budget (1e9 bytes)")
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--team-size", type=int, default=0, help="batch: workgroups per team (0: autotune table)")
     ap.add_argument("--team-min-bytes", type=int, default=0, help="batch: team threshold (0: autotune table)")
@@ -171,6 +277,8 @@ def main():
 
     if args.workload == "batch":
         return batch_bench(args)
+    if args.workload == "serve":
+        return serve_bench(args)
 
     import numpy as np
     import torch

@@ -155,15 +155,16 @@ typedef struct lpd_batch_options {
     double eps_p;
     int64_t max_iter;        /* per LP; < 0: 50*(m_i+n_i); 0 allowed */
     int32_t team_size;       /* workgroups per team for large LPs: > 1 one fixed size for
-                                all of them, 1 no teams, 0 the autotune table's choice
-                                (built-in default: sized per LP, see below) */
+                                all of them, 1 no teams, 0 sized per LP if
+                                team_bytes_per_wg > 0, else the autotune table's choice
+                                (built-in default: sized per LP) */
     int32_t grid_blocks;     /* workgroups of the launch (0: one per CU) */
     int64_t team_min_bytes;  /* tableau bytes from which an LP is solved by a team
                                 (0: autotune table; < 0: never) */
     int64_t *iterations;     /* device, count entries, optional: pivots of each LP */
-    int64_t team_bytes_per_wg; /* team_size 0: an LP of B tableau bytes gets a team of
+    int64_t team_bytes_per_wg; /* per-LP sizing: an LP of B tableau bytes gets a team of
                                   the largest power of two <= B / team_bytes_per_wg
-                                  workgroups (0: autotune table) */
+                                  workgroups, capped by the grid (0: autotune table) */
 } lpd_batch_options;
 
 /*
@@ -207,6 +208,9 @@ int lp_solve_batch(int32_t count, const int64_t *m, const int64_t *n, const doub
  * lp_solve_dense call, so x / obj / status / iterations are bit-identical to
  * a solve of it alone, whatever else is resident.
  *
+ * Inputs of requests admitted while an epoch runs are copied on a second
+ * stream and join the next epoch.
+ *
  * Footprint of an m x n request: every device byte it holds while resident,
  * the tableau workspace (8 (m+1)(n+m+1) bytes, rows padded to 32 doubles)
  * plus a copy of A, b, c and x.  LPs whose tableau fits in LDS need no
@@ -219,12 +223,19 @@ typedef struct lpd_server_options {
     double eps_d;              /* as lpd_options (<= 0: 1e-9) */
     double eps_p;
     int64_t max_iter;          /* per LP (0 or < 0: 50*(m+n)) */
-    int64_t pivots_per_epoch;  /* pivots each resident LP may do per launch (<= 0: 32) */
+    int64_t pivots_per_epoch;  /* pivots each resident LP may do per launch; <= 0: sized
+                                  per LP so that every workgroup streams about
+                                  epoch_bytes_per_wg tableau bytes per launch */
     int32_t max_resident;      /* most LPs resident at once (<= 0: 4096) */
     int32_t reserved;
-    int64_t team_min_bytes;    /* as lpd_batch_options (0: autotune table) */
-    int64_t team_bytes_per_wg; /* as lpd_batch_options (0: autotune table); teams are
-                                  always sized per LP */
+    int64_t team_min_bytes;    /* tableau bytes from which an LP may get a team
+                                  (0: twice team_bytes_per_wg; < 0: never) */
+    int64_t team_bytes_per_wg; /* least tableau bytes per workgroup of a team (<= 0:
+                                  256 KiB); workgroups are shared out in proportion to
+                                  the tableau bytes of the resident LPs */
+    int64_t epoch_bytes_per_wg; /* see pivots_per_epoch (<= 0: 256 MiB) */
+    int64_t admit_bytes_per_round; /* input bytes copied per admission step at most
+                                      (at least one request; <= 0: 512 MiB) */
 } lpd_server_options;
 
 /* One finished request, as returned by lpd_server_poll. */
@@ -249,6 +260,9 @@ typedef struct lpd_server_stats {
     uint64_t used_bytes;        /* footprint of the resident LPs now */
     uint64_t peak_bytes;        /* largest used_bytes ever reached */
     uint64_t budget_bytes;
+    uint64_t copy_bytes;        /* input bytes copied to the device so far */
+    double kernel_seconds;      /* device time of the epoch launches (HIP events) */
+    double admit_host_seconds;  /* worker time spent issuing admission copies */
 } lpd_server_stats;
 
 /* Creates a server on HIP device `device` with a footprint budget in bytes.

@@ -264,11 +264,20 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     if (opt->grid_blocks > 0) nblocks = opt->grid_blocks;
     iterations = opt->iterations;
   }
-  // Unset knobs (0) come from the autotune table.
+  // Unset knobs (0) come from the autotune table.  A team size > 0 fixes the
+  // size; else a given team_bytes_per_wg asks for per-LP sizing; else the
+  // table decides both.
   BatchKnobs knobs;
-  knobs.team_size = team_size > 0 ? team_size : tuning().team_size;
+  if (team_size > 0) {
+    knobs.team_size = team_size;
+  } else if (per_wg > 0) {
+    knobs.team_size = 0;
+    knobs.team_bytes_per_wg = per_wg;
+  } else {
+    knobs.team_size = tuning().team_size;
+    knobs.team_bytes_per_wg = tuning().team_bytes_per_wg;
+  }
   knobs.team_min_bytes = team_min != 0 ? team_min : tuning().team_min_bytes;
-  knobs.team_bytes_per_wg = per_wg > 0 ? per_wg : tuning().team_bytes_per_wg;
 
   BatchPlan P = plan_batch(count, m, n, knobs, nblocks);
   if (!P.ok) return LPD_ERR_TOO_LARGE;

@@ -53,6 +53,12 @@ struct BatchKnobs {
   int64_t team_min_bytes = 0;      // tableau bytes from which an LP gets a team (< 0: never)
   int64_t team_bytes_per_wg = 0;   // per-LP team sizing: tableau bytes per workgroup
   bool own_workspaces = false;     // every non-LDS LP brings its own workspace (BatchItem::ws)
+  // Share sizing (team_size 0 only): every non-LDS LP gets workgroups in
+  // proportion to its tableau bytes, at most one per share_min_bytes_per_wg,
+  // one team per LP, so that all of them advance at once (epochs of the
+  // serving runtime, where each LP does a bounded number of pivots).
+  bool share = false;
+  int64_t share_min_bytes_per_wg = 0;
 };
 
 // Host plan: classes, queue orders, LDS and workspace sizes.

@@ -124,6 +124,10 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   int64_t max_vw = 1;
   size_t lds_wg = 0;
   double w_single = 0.0;
+  double share_total = 0.0;  // tableau bytes of the LPs that do not fit in LDS
+  if (K.share)
+    for (int32_t i = 0; i < count; ++i)
+      if (wg_lds_bytes(m[i], n[i]) > limit) share_total += tableau_bytes(m[i], n[i]);
   for (int32_t i = 0; i < count; ++i) {
     const double bytes = tableau_bytes(m[i], n[i]);
     work[(size_t)i] = bytes * (double)(m[i] + n[i]);  // proxy: tableau size x pivot-count scale
@@ -135,8 +139,14 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
       max_vw = std::max<int64_t>(max_vw, (n[i] + m[i] + 1) / 2);
       if (K.team_min_bytes >= 0 && bytes >= (double)K.team_min_bytes) {
         int s = 0;
-        if (K.team_size > 0) s = K.team_size;
-        else if (K.team_bytes_per_wg > 0) s = pow2_floor((int64_t)(bytes / (double)K.team_bytes_per_wg));
+        if (K.team_size > 0) {
+          s = K.team_size;
+        } else if (K.share) {
+          const double cap = K.share_min_bytes_per_wg > 0 ? bytes / (double)K.share_min_bytes_per_wg : 1e18;
+          s = pow2_floor((int64_t)std::min(cap, (double)nblocks * bytes / share_total));
+        } else if (K.team_bytes_per_wg > 0) {
+          s = pow2_floor((int64_t)(bytes / (double)K.team_bytes_per_wg));
+        }
         s = std::min(s, nblocks);
         if (s >= 2) {
           P.klass[(size_t)i] = kClassTeam;
@@ -186,6 +196,7 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   for (int c = 0; c < P.n_classes; ++c) {
     int s = sizes[(size_t)c];
     int g = (int)(nblocks * (wc[c] / std::max(w_all, 1.0)));
+    if (K.share) g = (int)cl[c].size() * s;  // one team per LP
     g = std::max(s, g / s * s);
     g = std::min<int>(g, (int)cl[c].size() * s);
     P.cls_size[c] = s;

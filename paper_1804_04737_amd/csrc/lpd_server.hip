@@ -1,26 +1,31 @@
 // Serving runtime: continuous batching of dense LPs on one GPU.
 //
 // Requests arrive from any host thread (lpd_server_submit).  A worker thread
-// owns one HIP stream and repeats epochs:
-//   1. admission: waiting requests, in arrival order, become resident while
-//      their device footprint fits in the memory budget; their A, b, c are
-//      copied to HBM and their solve state starts at "not started";
-//   2. one batched launch over every resident LP (lpd_batch.hip): each LP
-//      advances by at most `pivots_per_epoch` pivots and keeps its tableau and
-//      scalars in HBM between epochs (LPs small enough for LDS finish in one
-//      epoch);
-//   3. statuses come back; finished LPs copy x, obj, pivots to the caller's
-//      host buffers, their memory returns to the budget and a completion with
-//      host timestamps is queued for lpd_server_poll.
-// A request that arrives while others run is admitted in the next epoch, so
-// work from different requests overlaps on the device.  Every LP performs
-// exactly the pivots of its own lp_solve_dense call, so its result is
-// bit-identical alone and in any mix.
+// drives two HIP streams (both at the default priority) in a pipeline:
+//   admission  waiting requests, in arrival order, become resident while their
+//              device footprint fits in what the budget has left; their A, b,
+//              c go to HBM on the copy stream while the current epoch runs;
+//   epoch      one batched launch (lpd_batch.hip) over every resident LP on
+//              the compute stream: each LP advances by a bounded number of
+//              pivots and keeps its tableau and scalars in HBM between epochs
+//              (LPs small enough for LDS finish within one epoch).
+//              Workgroups are shared out in proportion to the tableau bytes
+//              of the resident LPs, one team per LP, and each LP's pivot
+//              budget is sized so that every workgroup streams about the same
+//              bytes per epoch: all of them advance together and finish the
+//              epoch at about the same time;
+//   retire     statuses come back; finished LPs copy x to the caller's host
+//              buffer, their memory returns to the budget and a completion
+//              with host timestamps is queued for lpd_server_poll.
+// Requests admitted during epoch E join epoch E+1 (the compute stream waits
+// for their copies), so work from different requests overlaps on the device.
+// Every LP performs exactly the pivots of its own lp_solve_dense call, so its
+// result is bit-identical alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cmath>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -60,6 +65,10 @@ uint64_t footprint_of(int64_t m, int64_t n, bool lds) {
   return input_bytes(m, n) + (lds ? 0 : grid_layout(m, n, 1).total);
 }
 
+// Smallest tableau share a workgroup gets under share sizing: below this the
+// per-pivot barrier costs more than the workgroup's part of the sweep.
+constexpr int64_t kShareMinBytesPerWg = 256 << 10;
+
 }  // namespace
 }  // namespace lpd
 
@@ -70,9 +79,13 @@ struct lpd_server {
   uint64_t budget = 0;
   lpd_server_options opt{};
   BatchKnobs knobs;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // compute: epochs, result copies, frees
+  hipStream_t copy_stream = nullptr;  // admission: allocations and input copies
+  hipEvent_t ev_staged = nullptr;     // end of the last admission round's copies
+  hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the epoch launch
   // Slot tables (device): status, objective, pivots and solve state of each
-  // resident LP, with pinned host mirrors.
+  // resident LP, with pinned host mirrors.  init_status / init_state are
+  // pinned constants (-1, not started) that fresh slots are copied from.
   int32_t* d_status = nullptr;
   double* d_obj = nullptr;
   int64_t* d_iter = nullptr;
@@ -80,7 +93,8 @@ struct lpd_server {
   int32_t* h_status = nullptr;
   double* h_obj = nullptr;
   int64_t* h_iter = nullptr;
-  SolveState* h_state = nullptr;
+  int32_t* init_status = nullptr;
+  SolveState* init_state = nullptr;
   int32_t nslots = 0;
   int nblocks = 0;
   size_t lds_limit = 0;
@@ -97,14 +111,18 @@ struct lpd_server {
   uint64_t used = 0;          // footprint of admitted requests (under mu)
   lpd_server_stats stats{};   // under mu
   // worker-only state
-  std::vector<Request> resident;
+  std::vector<Request> resident, staged;
   std::vector<int32_t> free_slots;
+  bool in_flight = false;
+  hipError_t epoch_err = hipSuccess;
   std::thread worker;
   Clock::time_point t0;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
   void run();
-  void epoch();
+  void admit();
+  void launch_epoch();
+  void retire_epoch();
   void release(Request& r);
   void complete(Request& r, int32_t status, double obj, int64_t iters);
 };
@@ -126,56 +144,6 @@ void lpd_server::complete(Request& r, int32_t status, double obj, int64_t iters)
   stats.completed += 1;
 }
 
-void lpd_server::run() {
-  (void)hipSetDevice(device);
-  for (;;) {
-    std::vector<Request> admit;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !pending.empty() || !resident.empty(); });
-      if (stop && pending.empty() && resident.empty()) return;
-      // Admission in arrival order while the budget and the slot table allow.
-      while (!pending.empty() && (int32_t)(resident.size() + admit.size()) < nslots) {
-        Request& r = pending.front();
-        if (used + r.footprint > budget) break;
-        r.t_admit = now();
-        used += r.footprint;
-        stats.peak_bytes = std::max<uint64_t>(stats.peak_bytes, used);
-        admit.push_back(r);
-        pending.pop_front();
-      }
-      stats.resident = (int64_t)(resident.size() + admit.size());
-      stats.waiting = (int64_t)pending.size();
-    }
-    for (Request& r : admit) {
-      hipError_t e = hipMallocAsync((void**)&r.dmem, r.footprint, stream);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        release(r);
-        complete(r, e == hipErrorOutOfMemory ? LPD_ERR_OUT_OF_MEMORY : LPD_ERR_HIP, 0.0, 0);
-        continue;
-      }
-      r.slot = free_slots.back();
-      free_slots.pop_back();
-      r.dA = reinterpret_cast<double*>(r.dmem);
-      r.db = r.dA + r.m * r.n;
-      r.dc = r.db + r.m;
-      r.dx = r.dc + r.n;
-      r.dws = r.dmem + input_bytes(r.m, r.n);
-      (void)hipMemcpyAsync(r.dA, r.A, 8 * (size_t)(r.m * r.n), hipMemcpyHostToDevice, stream);
-      (void)hipMemcpyAsync(r.db, r.b, 8 * (size_t)r.m, hipMemcpyHostToDevice, stream);
-      (void)hipMemcpyAsync(r.dc, r.c, 8 * (size_t)r.n, hipMemcpyHostToDevice, stream);
-      // Fresh slot: status "running", solve not started.
-      h_status[r.slot] = -1;
-      h_state[r.slot] = SolveState{};
-      (void)hipMemcpyAsync(d_status + r.slot, h_status + r.slot, 4, hipMemcpyHostToDevice, stream);
-      (void)hipMemcpyAsync(d_state + r.slot, h_state + r.slot, sizeof(SolveState), hipMemcpyHostToDevice, stream);
-      resident.push_back(r);
-    }
-    if (!resident.empty()) epoch();
-  }
-}
-
 void lpd_server::release(Request& r) {
   if (r.dmem) (void)hipFreeAsync(r.dmem, stream);
   r.dmem = nullptr;
@@ -185,19 +153,97 @@ void lpd_server::release(Request& r) {
   used -= r.footprint;
 }
 
-void lpd_server::epoch() {
+void lpd_server::run() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (!in_flight && resident.empty() && staged.empty())
+        cv.wait(lk, [&] { return stop || !pending.empty(); });
+      if (stop && pending.empty() && !in_flight && resident.empty() && staged.empty()) return;
+    }
+    admit();  // its copies overlap the epoch in flight
+    if (in_flight) retire_epoch();
+    if (!staged.empty()) {
+      (void)hipStreamWaitEvent(stream, ev_staged, 0);
+      for (Request& r : staged) resident.push_back(r);
+      staged.clear();
+    }
+    if (!resident.empty()) launch_epoch();
+  }
+}
+
+// Admission in arrival order while the budget and the slot table allow; the
+// admitted requests' inputs go to HBM on the copy stream.
+void lpd_server::admit() {
+  std::vector<Request> batch;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    uint64_t round_bytes = 0;
+    while (!pending.empty() && batch.size() < free_slots.size()) {
+      Request& r = pending.front();
+      if (used + r.footprint > budget) break;
+      // Bounded copy work per step, so that retiring and relaunching are not
+      // held up behind a burst of admissions.
+      const uint64_t in = 8 * (uint64_t)(r.m * r.n + r.m + r.n);
+      if (!batch.empty() && round_bytes + in > (uint64_t)opt.admit_bytes_per_round) break;
+      round_bytes += in;
+      r.t_admit = now();
+      used += r.footprint;
+      stats.peak_bytes = std::max<uint64_t>(stats.peak_bytes, used);
+      batch.push_back(r);
+      pending.pop_front();
+    }
+    stats.resident = (int64_t)(resident.size() + staged.size() + batch.size());
+    stats.waiting = (int64_t)pending.size();
+  }
+  if (batch.empty()) return;
+  const Clock::time_point h0 = Clock::now();
+  uint64_t bytes = 0;
+  for (Request& r : batch) {
+    hipError_t e = hipMallocAsync((void**)&r.dmem, r.footprint, copy_stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      r.dmem = nullptr;
+      release(r);
+      complete(r, e == hipErrorOutOfMemory ? LPD_ERR_OUT_OF_MEMORY : LPD_ERR_HIP, 0.0, 0);
+      continue;
+    }
+    r.slot = free_slots.back();
+    free_slots.pop_back();
+    r.dA = reinterpret_cast<double*>(r.dmem);
+    r.db = r.dA + r.m * r.n;
+    r.dc = r.db + r.m;
+    r.dx = r.dc + r.n;
+    r.dws = r.dmem + input_bytes(r.m, r.n);
+    (void)hipMemcpyAsync(r.dA, r.A, 8 * (size_t)(r.m * r.n), hipMemcpyHostToDevice, copy_stream);
+    (void)hipMemcpyAsync(r.db, r.b, 8 * (size_t)r.m, hipMemcpyHostToDevice, copy_stream);
+    (void)hipMemcpyAsync(r.dc, r.c, 8 * (size_t)r.n, hipMemcpyHostToDevice, copy_stream);
+    (void)hipMemcpyAsync(d_status + r.slot, init_status + r.slot, 4, hipMemcpyHostToDevice, copy_stream);
+    (void)hipMemcpyAsync(d_state + r.slot, init_state + r.slot, sizeof(SolveState), hipMemcpyHostToDevice,
+                         copy_stream);
+    bytes += 8 * (uint64_t)(r.m * r.n + r.m + r.n);
+    staged.push_back(r);
+  }
+  (void)hipEventRecord(ev_staged, copy_stream);
+  std::lock_guard<std::mutex> g(mu);
+  stats.admit_host_seconds += std::chrono::duration<double>(Clock::now() - h0).count();
+  stats.copy_bytes += bytes;
+}
+
+void lpd_server::launch_epoch() {
   const int32_t count = (int32_t)resident.size();
   std::vector<int64_t> m((size_t)count), n((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
     m[(size_t)i] = resident[(size_t)i].m;
     n[(size_t)i] = resident[(size_t)i].n;
   }
-  BatchPlan P = plan_batch(count, m.data(), n.data(), knobs, nblocks);
+  BatchPlan P = plan_batch(count, m.data(), n.data(), knobs, nblocks, lds_limit);
   hipError_t e = P.ok ? hipSuccess : hipErrorInvalidValue;
   if (e == hipSuccess) {
     const int maxb = batch_max_blocks(P.lds_bytes);
     if (maxb <= 0) e = hipErrorInvalidValue;
-    else if (nblocks > maxb) P = plan_batch(count, m.data(), n.data(), knobs, maxb);
+    else if (nblocks > maxb) P = plan_batch(count, m.data(), n.data(), knobs, maxb, lds_limit);
   }
   std::vector<BatchItem> items((size_t)count);
   for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
@@ -218,9 +264,16 @@ void lpd_server::epoch() {
     a.status = d_status + r.slot;
     a.iterations = d_iter + r.slot;
     a.state = d_state + r.slot;
-    a.pivot_budget = opt.pivots_per_epoch;
     it.klass = P.klass[(size_t)i];
     it.tclass = P.tclass[(size_t)i];
+    if (opt.pivots_per_epoch > 0) {
+      a.pivot_budget = opt.pivots_per_epoch;
+    } else {
+      // A pivot streams the tableau twice (read, write), split over the team.
+      const double team = it.klass == kClassTeam ? (double)P.cls_size[it.tclass] : 1.0;
+      const double k = (double)opt.epoch_bytes_per_wg * team / (2.0 * tableau_bytes(r.m, r.n));
+      a.pivot_budget = (int64_t)std::max(1.0, std::min(k, 1e9));
+    }
     it.ws = r.dws;
     // The planner's LDS test is the one submit used; never launch an LP
     // without the workspace its class walks over.
@@ -233,17 +286,29 @@ void lpd_server::epoch() {
     e = hipMallocAsync(&meta, P.total, stream);
     if (e == hipSuccess) meta_bytes = P.total;
   }
+  (void)hipEventRecord(ev_k0, stream);
   if (e == hipSuccess) e = launch_batch(P, items, meta, stream);
+  (void)hipEventRecord(ev_k1, stream);
   if (e != hipSuccess) (void)hipGetLastError();
   // Statuses, objectives and pivot counts of every slot in one copy each.
   (void)hipMemcpyAsync(h_status, d_status, 4 * (size_t)nslots, hipMemcpyDeviceToHost, stream);
   (void)hipMemcpyAsync(h_obj, d_obj, 8 * (size_t)nslots, hipMemcpyDeviceToHost, stream);
   (void)hipMemcpyAsync(h_iter, d_iter, 8 * (size_t)nslots, hipMemcpyDeviceToHost, stream);
+  epoch_err = e;
+  in_flight = true;
+}
+
+void lpd_server::retire_epoch() {
+  in_flight = false;
+  hipError_t e = epoch_err;
   const hipError_t es = hipStreamSynchronize(stream);
   if (e == hipSuccess) e = es;
+  float ms = 0.f;
+  const bool timed = e == hipSuccess && hipEventElapsedTime(&ms, ev_k0, ev_k1) == hipSuccess;
   {
     std::lock_guard<std::mutex> g(mu);
     stats.epochs += 1;
+    if (timed) stats.kernel_seconds += ms * 1e-3;
   }
   std::vector<Request> still, fin;
   for (Request& r : resident) {
@@ -274,20 +339,23 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   hipDeviceProp_t p;
   if (hipGetDeviceProperties(&p, device) != hipSuccess || std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
     return nullptr;
-  if (hipSetDevice(device) != hipSuccess) return nullptr;
   if (opt && (std::isnan(opt->eps_d) || std::isnan(opt->eps_p))) return nullptr;
+  if (hipSetDevice(device) != hipSuccess) return nullptr;
   lpd_server* s = new lpd_server();
   s->device = device;
   s->budget = budget_bytes;
   if (opt) s->opt = *opt;
   if (!(s->opt.eps_d > 0)) s->opt.eps_d = LPD_DEFAULT_EPS;
   if (!(s->opt.eps_p > 0)) s->opt.eps_p = LPD_DEFAULT_EPS;
-  if (s->opt.pivots_per_epoch <= 0) s->opt.pivots_per_epoch = 32;
+  if (s->opt.pivots_per_epoch < 0) s->opt.pivots_per_epoch = 0;
+  if (s->opt.epoch_bytes_per_wg <= 0) s->opt.epoch_bytes_per_wg = 256ll << 20;
+  if (s->opt.admit_bytes_per_round <= 0) s->opt.admit_bytes_per_round = 512ll << 20;
   if (s->opt.max_resident <= 0) s->opt.max_resident = 4096;
-  const BatchKnobs tuned = tuned_batch_knobs();
-  s->knobs.team_size = 0;  // teams sized per LP
-  s->knobs.team_min_bytes = s->opt.team_min_bytes != 0 ? s->opt.team_min_bytes : tuned.team_min_bytes;
-  s->knobs.team_bytes_per_wg = s->opt.team_bytes_per_wg > 0 ? s->opt.team_bytes_per_wg : tuned.team_bytes_per_wg;
+  s->knobs.team_size = 0;
+  s->knobs.share = true;
+  s->knobs.share_min_bytes_per_wg = s->opt.team_bytes_per_wg > 0 ? s->opt.team_bytes_per_wg : kShareMinBytesPerWg;
+  // Default threshold: any LP that could fill a team of two.
+  s->knobs.team_min_bytes = s->opt.team_min_bytes != 0 ? s->opt.team_min_bytes : 2 * s->knobs.share_min_bytes_per_wg;
   s->knobs.own_workspaces = true;
   s->nslots = s->opt.max_resident;
   s->nblocks = p.multiProcessorCount;
@@ -303,6 +371,10 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   }
   const size_t ns = (size_t)s->nslots;
   bool ok = hipStreamCreate(&s->stream) == hipSuccess;
+  ok = ok && hipStreamCreate(&s->copy_stream) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&s->ev_staged, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreate(&s->ev_k0) == hipSuccess;
+  ok = ok && hipEventCreate(&s->ev_k1) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->d_status, 4 * ns) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->d_obj, 8 * ns) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->d_iter, 8 * ns) == hipSuccess;
@@ -310,12 +382,17 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   ok = ok && hipHostMalloc((void**)&s->h_status, 4 * ns, 0) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&s->h_obj, 8 * ns, 0) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&s->h_iter, 8 * ns, 0) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&s->h_state, sizeof(SolveState) * ns, 0) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&s->init_status, 4 * ns, 0) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&s->init_state, sizeof(SolveState) * ns, 0) == hipSuccess;
   (void)hipSetDevice(prev);
   if (!ok) {
     (void)hipGetLastError();
     lpd_server_destroy(s);
     return nullptr;
+  }
+  for (size_t i = 0; i < ns; ++i) {
+    s->init_status[i] = -1;
+    s->init_state[i] = SolveState{};
   }
   for (int32_t i = s->nslots - 1; i >= 0; --i) s->free_slots.push_back(i);
   s->t0 = Clock::now();
@@ -383,6 +460,7 @@ void lpd_server_destroy(lpd_server* s) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(s->device);
+  if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
   if (s->stream) {
     if (s->meta) (void)hipFreeAsync(s->meta, s->stream);
     (void)hipStreamSynchronize(s->stream);
@@ -394,7 +472,11 @@ void lpd_server_destroy(lpd_server* s) {
   (void)hipHostFree(s->h_status);
   (void)hipHostFree(s->h_obj);
   (void)hipHostFree(s->h_iter);
-  (void)hipHostFree(s->h_state);
+  (void)hipHostFree(s->init_status);
+  (void)hipHostFree(s->init_state);
+  for (hipEvent_t ev : {s->ev_staged, s->ev_k0, s->ev_k1})
+    if (ev) (void)hipEventDestroy(ev);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   (void)hipSetDevice(prev);
   delete s;

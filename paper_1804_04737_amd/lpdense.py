@@ -52,7 +52,8 @@ class BatchOptions(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
                 ("pivots_per_epoch", _I64), ("max_resident", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("team_min_bytes", _I64), ("team_bytes_per_wg", _I64)]
+                ("reserved", ctypes.c_int32), ("team_min_bytes", _I64), ("team_bytes_per_wg", _I64),
+                ("epoch_bytes_per_wg", _I64), ("admit_bytes_per_round", _I64)]
 
 
 class Completion(ctypes.Structure):
@@ -65,7 +66,8 @@ class Completion(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", _I64), ("completed", _I64), ("epochs", _I64), ("resident", _I64),
                 ("waiting", _I64), ("used_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
-                ("budget_bytes", ctypes.c_uint64)]
+                ("budget_bytes", ctypes.c_uint64), ("copy_bytes", ctypes.c_uint64),
+                ("kernel_seconds", ctypes.c_double), ("admit_host_seconds", ctypes.c_double)]
 
 
 class LpdError(RuntimeError):
@@ -301,6 +303,8 @@ class Served:
     t_arrive: float      # seconds since the server started
     t_admit: float
     t_done: float
+    m: int = 0
+    n: int = 0
 
     @property
     def latency(self) -> float:
@@ -316,9 +320,11 @@ class Server:
 
     def __init__(self, budget_bytes: int, *, device: int = 0, pivots_per_epoch: int = 0,
                  max_resident: int = 0, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = 0,
-                 team_min_bytes: int = 0, team_bytes_per_wg: int = 0):
+                 team_min_bytes: int = 0, team_bytes_per_wg: int = 0, epoch_bytes_per_wg: int = 0,
+                 admit_bytes_per_round: int = 0):
         opts = ServerOptions(float(eps_d), float(eps_p), int(max_iter), int(pivots_per_epoch),
-                             int(max_resident), 0, int(team_min_bytes), int(team_bytes_per_wg))
+                             int(max_resident), 0, int(team_min_bytes), int(team_bytes_per_wg),
+                             int(epoch_bytes_per_wg), int(admit_bytes_per_round))
         self._lib = load()
         h = self._lib.lpd_server_create(int(device), int(budget_bytes), ctypes.byref(opts))
         if not h:
@@ -354,7 +360,8 @@ class Server:
                 cp = self._buf[i]
                 _, _, _, x = self._live.pop(int(cp.id))
                 out.append(Served(int(cp.id), int(cp.status), float(cp.obj), int(cp.iterations), x,
-                                  float(cp.t_arrive), float(cp.t_admit), float(cp.t_done)))
+                                  float(cp.t_arrive), float(cp.t_admit), float(cp.t_done),
+                                  int(cp.m), int(cp.n)))
             if k < len(self._buf):
                 return out
 
