@@ -67,6 +67,7 @@ struct GridWork {
   double* rhs[2];  // right-hand side, rows 0..m (row m = objective value), by parity
   int32_t* basis;  // m: basic variable of each row
   int32_t* pos;    // n+m: row of each basic variable, -1 if nonbasic
+  uint32_t* tickets;   // chunk tickets of the sweep's dynamic part: [0] and [32], by pivot parity
   BarrierSlot* slots; // 2 * nblocks
   int32_t cap_cap;     // capacity of the LDS capture list (entries)
   int32_t lds_vecs;    // capacity of the LDS pivot-row buffer (16-byte vectors, >= vw)
@@ -75,7 +76,7 @@ struct GridWork {
 // Sizes of the grid workspace pieces (bytes, each rounded to 256).
 struct GridLayout {
   int64_t ld, vw;
-  uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_slots, total;
+  uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_tickets, off_slots, total;
 };
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
@@ -98,6 +99,7 @@ __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblo
   L.off_rhs = take(2ull * (uint64_t)(m + 1) * 8);
   L.off_basis = take((uint64_t)m * 4);
   L.off_pos = take((uint64_t)(n + m) * 4);
+  L.off_tickets = take(256);  // two counters on separate 128 B lines
   L.off_slots = take(2ull * nblocks * sizeof(BarrierSlot));
   L.total = off;
   return L;
@@ -118,6 +120,7 @@ __host__ __device__ inline GridWork make_grid_work(const GridLayout& L, int64_t 
   }
   w.basis = reinterpret_cast<int32_t*>(base + L.off_basis);
   w.pos = reinterpret_cast<int32_t*>(base + L.off_pos);
+  w.tickets = reinterpret_cast<uint32_t*>(base + L.off_tickets);
   w.slots = reinterpret_cast<BarrierSlot*>(base + L.off_slots);
   return w;
 }

@@ -50,6 +50,7 @@ constexpr int kTicks = 8;         // phase_ticks entries per pivot
 constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column elements per workgroup)
 constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
+constexpr int kChunkSteps = 8;                 // dynamic sweep chunk: 8 x NT vectors
 
 __device__ __forceinline__ dbl2 ld_stream(const dbl2* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, p); }
@@ -169,6 +170,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   double* cap_r = cap_a + w.cap_cap;
   int32_t* cap_i = reinterpret_cast<int32_t*>(cap_r + w.cap_cap);
   int32_t* cap_count = cap_i + w.cap_cap;
+  uint32_t* s_tk = reinterpret_cast<uint32_t*>(cap_count + 1);  // 2 ticket broadcast slots
   if (threadIdx.x == 0) *cap_count = 0;
 
   const int nb = tm.size, tid = threadIdx.x;
@@ -186,6 +188,19 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const int32_t pub_v0 = (int32_t)((int64_t)vw * tm.rank / nb);
   const int32_t pub_v1 = (int32_t)((int64_t)vw * (tm.rank + 1) / nb);
   uint32_t& epoch = *tm.epoch;
+  // Guided split of each sweep: the first elements (flat index below
+  // e_static) follow the static grid-stride walk; the last ~1/8, in chunks
+  // of kChunkSteps x NT vectors, go to whichever workgroup of the team asks
+  // next (atomic ticket counter), so that workgroups that ran slower this
+  // pivot leave their share of the tail to faster ones.
+  const int64_t e_total = (int64_t)m * vw;
+  const int64_t steps_total = (e_total + G - 1) / G;
+  const bool dyn = nb > 1 && steps_total >= 8;
+  const int64_t e_static = dyn ? (steps_total - steps_total / 8) * G : e_total;
+  const int64_t chunk = (int64_t)kChunkSteps * NT;
+  const uint32_t n_chunks = dyn ? (uint32_t)((e_total - e_static + chunk - 1) / chunk) : 0u;
+  const int64_t n_static = e_static > gid ? (e_static - gid - 1) / G + 1 : 0;
+  const int32_t dq_q = (int32_t)(NT / vw), dq_r = (int32_t)(NT % vw);
 
   int32_t status = -1;
   int64_t iter = 0;
@@ -242,6 +257,12 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     }
     for (int64_t j = gid; j < ncols; j += G) w.pos[j] = j < n ? -1 : (int32_t)(j - n);
 
+    // Zeroed whatever the team size: a resumable solve may be continued by a
+    // larger team in a later launch.
+    if (leader && tid == 0) {
+      __hip_atomic_store(w.tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(w.tickets + 32, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     {
       Cand f0 = cand_none();
       f0.flags = flags;
@@ -295,6 +316,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     ++done_here;
     uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
     if (tk && tid == 0) tk[0] = __builtin_amdgcn_s_memrealtime();
+    // The previous pivot's ticket counter is idle until the next pivot (every
+    // workgroup passed the last barrier after its final ticket): reset it.
+    if (dyn && leader && tid == 0)
+      __hip_atomic_store(w.tickets + 32 * ((iter + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int cur = (int)(iter & 1), nxt = cur ^ 1;
     double* obj_nxt = w.obj[nxt];
     const double* rhs_cur = w.rhs[cur];
@@ -367,10 +392,50 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       const int32_t kv = kn >> 1, kh = kn & 1;
       const double eps_p = a.eps_p;
       const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
+      // One element (i, v) of the dynamic part: the same work as one step of
+      // the static walk below.
+      auto element = [&](int32_t i, int32_t v) {
+        const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
+        const double f = pcol_cur[i];
+        const bool cap = (v == kv);
+        double rh = 0.0;
+        if (cap) rh = rhs_cur[i];
+        const dbl2* src = (i == lprev) ? pr_prev : rowp;
+        dbl2 t;
+        if (i != l) t = ld_stream(src + v);
+        const dbl2 r = prow[v];
+        dbl2 nv;
+        if (i == l) {
+          nv = r;
+        } else {
+          nv.x = __builtin_fma(-f, r.x, t.x);
+          nv.y = __builtin_fma(-f, r.y, t.y);
+        }
+        if (cap) {
+          const double an = kh ? nv.y : nv.x;
+          const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
+          pcol_nxt[i] = an;
+          rhs_nxt[i] = rn;
+          const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
+          if (slot < w.cap_cap) {
+            cap_a[slot] = an;
+            cap_r[slot] = rn;
+            cap_i[slot] = i;
+          } else {
+            ratio_offer(rc, an, rn, i, eps_p);
+          }
+        }
+        if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
+      };
+      // The first ticket is requested before the static walk, which hides
+      // the atomic's latency (this pivot's counter was reset a pivot ago).
+      uint32_t* ctr = w.tickets + 32 * (iter & 1);
+      uint32_t nxt = 0;
+      if (dyn && tid == 0) nxt = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int32_t i = i_start, v = v_start;
       const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
       const int64_t row_step = (int64_t)step_q * ldv;
-      while (i < m) {
+      for (int64_t q = 0; q < n_static; ++q) {
         const double f = pcol_cur[i];
         const bool cap = (v == kv);
         double rh = 0.0;
@@ -414,6 +479,31 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           rowp += ldv;
         }
       }
+      if (dyn) {
+        // Dynamic tail of the sweep.  Ticket c covers flat elements
+        // e_static + c * chunk + [0, chunk); thread tid takes every NT-th.
+        // Lane 0 asks for the next ticket after its first element of the
+        // current chunk, so the atomic's latency hides behind that chunk.
+        for (int par = 0;; par ^= 1) {
+          if (tid == 0) s_tk[par] = nxt;
+          __syncthreads();
+          const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_tk[par]);
+          if (c >= n_chunks) break;
+          const int64_t e0 = e_static + (int64_t)c * chunk + tid;
+          int32_t ii = (int32_t)(e0 / vw), vv = (int32_t)(e0 % vw);
+          for (int qq = 0; qq < kChunkSteps; ++qq) {
+            if (ii < m) element(ii, vv);
+            if (qq == 0 && tid == 0)
+              nxt = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            vv += dq_r;
+            ii += dq_q;
+            if (vv >= vw) {
+              vv -= vw;
+              ++ii;
+            }
+          }
+        }
+      }
       __syncthreads();
       const int32_t ncap = min(*cap_count, w.cap_cap);
       for (int32_t e = tid; e < ncap; e += NT) ratio_offer(rc, cap_a[e], cap_r[e], cap_i[e], eps_p);
@@ -441,6 +531,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
 
   if (status < 0) {
     // Suspended: keep the scalars for the next call (all workgroups agree).
+    if (leader && tid == 0)
+      __hip_atomic_store(w.tickets + 32 * ((iter + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (leader && tid == 0) {
       a.state->phase = 1;
       a.state->k = k;

@@ -131,3 +131,25 @@ def test_server_rejects_and_edge_cases():
         got = _drain(srv, len(ids))
     for i, lp in zip(ids, lps):
         _check_vs_oracle(lp, got[i], max_iter=7)
+
+
+def test_server_lp_moves_from_one_workgroup_to_a_team():
+    """A small LP that shares the device with a large one runs on a single
+    workgroup (its share of the workgroups is below two); once the large LP
+    has left, the same LP continues on a team of two with the sweep's dynamic
+    tail.  The large LP (c = e_0) is optimal after one pivot, and one pivot per
+    epoch makes the hand-over happen after the first epochs.  Both results
+    must equal the oracle's bits."""
+    big_A, big_b, _ = lpgen.dense_lp(3000, 3000, 21)
+    big_c = np.zeros(3000)
+    big_c[0] = 1.0
+    small = lpgen.dense_lp(130, 150, 22)
+    announce("server: single workgroup then team of two")
+    with lpdense.Server(8 << 30, pivots_per_epoch=1, team_min_bytes=1, team_bytes_per_wg=150_000) as srv:
+        bid = srv.submit(big_A, big_b, big_c)
+        sid = srv.submit(*small)
+        got = _drain(srv, 2)
+        st = srv.stats()
+    assert st.epochs >= got[sid].iterations
+    _check_vs_oracle((big_A, big_b, big_c), got[bid])
+    _check_vs_oracle(small, got[sid])
