@@ -136,7 +136,7 @@ def batch_bench(args):
                    "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / args.steps), 1),
                    "effective_GBps": round(bytes_step / (el / args.steps) / 1e9, 1),
                    "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
-                   "one_at_a_time_effective_GBps": round(b1 / el1 / 1e9, 1),
+                   "one_at_a_time_effective_GBps": round(bytes_step / el1 / 1e9, 1),
                    "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
                    "team_size": args.team_size, "team_min_bytes": args.team_min_bytes},
     }

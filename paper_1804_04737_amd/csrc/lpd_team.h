@@ -51,6 +51,7 @@ constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column e
 constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
 constexpr int kChunkSteps = 8;                 // dynamic sweep chunk: 8 x NT vectors
+constexpr int64_t kDynMinSteps = 192;          // sweeps shorter than this are all static
 
 __device__ __forceinline__ dbl2 ld_stream(const dbl2* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, p); }
@@ -195,7 +196,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   // pivot leave their share of the tail to faster ones.
   const int64_t e_total = (int64_t)m * vw;
   const int64_t steps_total = (e_total + G - 1) / G;
-  const bool dyn = nb > 1 && steps_total >= 8;
+  // The dynamic part costs a few microseconds per pivot (ticket broadcasts,
+  // the last chunk's latency); it only pays off on long sweeps.
+  const bool dyn = nb > 1 && steps_total >= kDynMinSteps;
   const int64_t e_static = dyn ? (steps_total - steps_total / 8) * G : e_total;
   const int64_t chunk = (int64_t)kChunkSteps * NT;
   const uint32_t n_chunks = dyn ? (uint32_t)((e_total - e_static + chunk - 1) / chunk) : 0u;

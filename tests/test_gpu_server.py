@@ -134,22 +134,26 @@ def test_server_rejects_and_edge_cases():
 
 
 def test_server_lp_moves_from_one_workgroup_to_a_team():
-    """A small LP that shares the device with a large one runs on a single
-    workgroup (its share of the workgroups is below two); once the large LP
-    has left, the same LP continues on a team of two with the sweep's dynamic
-    tail.  The large LP (c = e_0) is optimal after one pivot, and one pivot per
-    epoch makes the hand-over happen after the first epochs.  Both results
-    must equal the oracle's bits."""
-    big_A, big_b, _ = lpgen.dense_lp(3000, 3000, 21)
-    big_c = np.zeros(3000)
-    big_c[0] = 1.0
-    small = lpgen.dense_lp(130, 150, 22)
+    """A 640 x 700 LP that shares the device with four 4000 x 4000 LPs runs
+    on a single workgroup (its share of the workgroups is below two); once
+    they have left, the same LP continues on a team of two whose sweeps are
+    long enough for the dynamic tail (ticket counters).  The large LPs
+    (c = e_0) are optimal after one pivot, and one pivot per epoch makes the
+    hand-over happen after the first epochs.  Every result must equal the
+    oracle's bits."""
+    bigs = []
+    for q in range(4):
+        A, b, _ = lpgen.dense_lp(4000, 4000, 30 + q)
+        c = np.zeros(4000)
+        c[0] = 1.0
+        bigs.append((A, b, c))
+    small = lpgen.dense_lp(640, 700, 22)
     announce("server: single workgroup then team of two")
-    with lpdense.Server(8 << 30, pivots_per_epoch=1, team_min_bytes=1, team_bytes_per_wg=150_000) as srv:
-        bid = srv.submit(big_A, big_b, big_c)
+    with lpdense.Server(16 << 30, pivots_per_epoch=1, team_min_bytes=1,
+                        team_bytes_per_wg=3_000_000) as srv:
+        bids = [srv.submit(*lp) for lp in bigs]
         sid = srv.submit(*small)
-        got = _drain(srv, 2)
-        st = srv.stats()
-    assert st.epochs >= got[sid].iterations
-    _check_vs_oracle((big_A, big_b, big_c), got[bid])
+        got = _drain(srv, 5)
+    for i, lp in zip(bids, bigs):
+        _check_vs_oracle(lp, got[i])
     _check_vs_oracle(small, got[sid])
