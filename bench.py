@@ -91,11 +91,12 @@ def batch_bench(args):
 
     from paper_1804_04737_amd import lpdense, lpgen
     lpdense.load()
-    lps = lpgen.batch_lps(args.batch_count, 32, 1024, args.seed)
+    lps = lpgen.batch_lps(args.batch_count, args.batch_lo, args.batch_hi, args.seed)
     pb = lpdense.pack_batch(lps)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    kw = dict(team_size=args.team_size, team_min_bytes=args.team_min_bytes, stream=stream)
+    kw = dict(team_size=args.team_size, team_min_bytes=args.team_min_bytes, wave_slots=args.wave_slots,
+              stream=stream)
     for _ in range(args.warmup):
         lpdense.solve_batch(pb, **kw)
     torch.cuda.synchronize()
@@ -131,14 +132,16 @@ def batch_bench(args):
         "metric": METRIC, "value": round(lps_s, 2), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batched: {args.batch_count} dense LPs, m and n log-uniform in [32, 1024], "
+        "config": {"workload": f"batched: {args.batch_count} dense LPs, m and n log-uniform in "
+                               f"[{args.batch_lo}, {args.batch_hi}], "
                                f"seed {args.seed}, one lp_solve_batch call per step",
                    "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / args.steps), 1),
                    "effective_GBps": round(bytes_step / (el / args.steps) / 1e9, 1),
                    "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
                    "one_at_a_time_effective_GBps": round(bytes_step / el1 / 1e9, 1),
                    "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
-                   "team_size": args.team_size, "team_min_bytes": args.team_min_bytes},
+                   "team_size": args.team_size, "team_min_bytes": args.team_min_bytes,
+                   "wave_slots": args.wave_slots},
     }
     print(json.dumps(out), flush=True)
 
@@ -266,6 +269,9 @@ def main():
                     help="serve: least tableau KiB per workgroup of a team (0: library default)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: footprint budget (1e9 bytes)")
     ap.add_argument("--batch-count", type=int, default=1024)
+    ap.add_argument("--batch-lo", type=int, default=32, help="batch: smallest m and n")
+    ap.add_argument("--batch-hi", type=int, default=1024, help="batch: largest m and n")
+    ap.add_argument("--wave-slots", type=int, default=0, help="batch: wave-per-instance slots (0: autotune table)")
     ap.add_argument("--team-size", type=int, default=0, help="batch: workgroups per team (0: autotune table)")
     ap.add_argument("--team-min-bytes", type=int, default=0, help="batch: team threshold (0: autotune table)")
     args = ap.parse_args()

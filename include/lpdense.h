@@ -165,6 +165,11 @@ typedef struct lpd_batch_options {
     int64_t team_bytes_per_wg; /* per-LP sizing: an LP of B tableau bytes gets a team of
                                   the largest power of two <= B / team_bytes_per_wg
                                   workgroups, capped by the grid (0: autotune table) */
+    int32_t wave_slots;      /* wave-per-instance: each workgroup's LDS is split into this
+                                many slices (<= 16) and an LP whose LDS tableau fits in one
+                                slice is solved by a single wave (0: autotune table, whose
+                                built-in default is off; < 0: off) */
+    int32_t reserved;
 } lpd_batch_options;
 
 /*
@@ -181,9 +186,10 @@ typedef struct lpd_batch_options {
  *   x_pack, x_off      device output pack and host offsets (n_i entries each)
  *   obj, status        device outputs, count entries each
  *   opt                may be NULL (defaults)
- * LPs whose tableau fits in LDS are solved by one workgroup in LDS; larger
- * ones by one workgroup over HBM, or by a team of workgroups if the tableau
- * is at least team_min_bytes.  Large LPs are started first.  Returns
+ * LPs whose tableau fits in a wave's slice of LDS (wave_slots) are solved by
+ * one wave each; others whose tableau fits in LDS by one workgroup in LDS;
+ * larger ones by one workgroup over HBM, or by a team of workgroups if the
+ * tableau is at least team_min_bytes.  Large LPs are started first.  Returns
  * LPD_SUCCESS or a negative lpd_error; asynchronous and stream-ordered like
  * lp_solve_dense.  Host arrays are only read during the call.
  */

@@ -103,6 +103,7 @@ struct Tuning {
   int team_size = 0;                    // 0: size teams per LP
   int64_t team_min_bytes = 2 << 20;
   int64_t team_bytes_per_wg = 2 << 20;
+  int wave_slots = 0;                   // 0: no wave-per-instance class
 };
 
 const Tuning& tuning() {
@@ -139,6 +140,8 @@ const Tuning& tuning() {
     t.team_min_bytes = num("team_min_bytes", t.team_min_bytes);
     const int64_t bw = num("team_bytes_per_wg", t.team_bytes_per_wg);
     if (bw > 0) t.team_bytes_per_wg = bw;
+    const int64_t ws = num("wave_slots", t.wave_slots);
+    if (ws >= 0 && ws <= 16) t.wave_slots = (int)ws;
   });
   return t;
 }
@@ -156,6 +159,7 @@ BatchKnobs tuned_batch_knobs() {
   k.team_size = tuning().team_size;
   k.team_min_bytes = tuning().team_min_bytes;
   k.team_bytes_per_wg = tuning().team_bytes_per_wg;
+  k.wave_slots = tuning().wave_slots;
   return k;
 }
 
@@ -248,7 +252,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
 
   double eps_d = LPD_DEFAULT_EPS, eps_p = LPD_DEFAULT_EPS;
   int64_t max_iter = -1, team_min = 0, per_wg = 0;
-  int team_size = 0, nblocks = dev.ncu;
+  int team_size = 0, nblocks = dev.ncu, wave_slots = 0;
   int64_t* iterations = nullptr;
   if (opt) {
     if (std::isnan(opt->eps_d) || std::isnan(opt->eps_p) || std::isinf(opt->eps_d) || std::isinf(opt->eps_p))
@@ -263,6 +267,8 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     per_wg = opt->team_bytes_per_wg;
     if (opt->grid_blocks > 0) nblocks = opt->grid_blocks;
     iterations = opt->iterations;
+    if (opt->wave_slots > 16) return LPD_ERR_INVALID_ARG;
+    wave_slots = opt->wave_slots;
   }
   // Unset knobs (0) come from the autotune table.  A team size > 0 fixes the
   // size; else a given team_bytes_per_wg asks for per-LP sizing; else the
@@ -278,6 +284,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     knobs.team_bytes_per_wg = tuning().team_bytes_per_wg;
   }
   knobs.team_min_bytes = team_min != 0 ? team_min : tuning().team_min_bytes;
+  knobs.wave_slots = wave_slots > 0 ? wave_slots : (wave_slots < 0 ? 0 : tuning().wave_slots);
 
   BatchPlan P = plan_batch(count, m, n, knobs, nblocks);
   if (!P.ok) return LPD_ERR_TOO_LARGE;

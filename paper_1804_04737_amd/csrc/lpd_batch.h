@@ -12,7 +12,8 @@ namespace lpd {
 enum : int32_t {
   kClassLds = 0,     // one workgroup, tableau in LDS (always runs to the end)
   kClassSingle = 1,  // one workgroup, grid walk over an HBM workspace
-  kClassTeam = 2     // a team of workgroups, grid walk over an HBM workspace
+  kClassTeam = 2,    // a team of workgroups, grid walk over an HBM workspace
+  kClassWave = 3     // one wave, tableau in the wave's slice of LDS (runs to the end)
 };
 
 constexpr int kMaxTeamClasses = 4;
@@ -39,9 +40,14 @@ struct BatchWork {
   const BatchItem* items;
   TeamClass cls[kMaxTeamClasses];
   int32_t n_classes;
-  uint32_t* counters;          // queue heads: [8 c] team class c, [8 kMaxTeamClasses] singles
+  uint32_t* counters;          // queue heads: [8 c] team class c, [8 kMaxTeamClasses] singles,
+                               // [8 (kMaxTeamClasses + 1)] one-wave LPs
   const int32_t* single_list;  // LP indices of the one-workgroup queue, big first
   int32_t n_single;
+  const int32_t* wave_list;    // LP indices of the one-wave queue, big first
+  int32_t n_wave;
+  int32_t wave_slots;          // waves per workgroup that take one-wave LPs
+  uint32_t wave_slice;         // LDS bytes of each such wave
   unsigned char* wg_ws;        // per-workgroup workspaces (null when not needed)
   uint64_t wg_ws_stride;
   int32_t cap_cap, lds_vecs;
@@ -59,6 +65,9 @@ struct BatchKnobs {
   // serving runtime, where each LP does a bounded number of pivots).
   bool share = false;
   int64_t share_min_bytes_per_wg = 0;
+  // Wave-per-instance: > 0 splits each workgroup's LDS into this many slices;
+  // an LP whose LDS tableau fits in one slice is solved by a single wave.
+  int wave_slots = 0;
 };
 
 // Host plan: classes, queue orders, LDS and workspace sizes.
@@ -71,7 +80,9 @@ struct BatchPlan {
   uint64_t cls_ws_stride[kMaxTeamClasses] = {};
   int32_t cap_cap = 0, lds_vecs = 0;
   size_t lds_bytes = 0;
-  std::vector<int32_t> klass, tclass, single_list;
+  std::vector<int32_t> klass, tclass, single_list, wave_list;
+  int32_t wave_slots = 0;
+  uint32_t wave_slice = 0;
   uint64_t wg_ws_stride = 0;
   uint64_t off_items = 0, off_lists = 0, off_counters = 0, off_slots = 0, off_team_ws = 0, off_wg_ws = 0;
   uint64_t total = 0;

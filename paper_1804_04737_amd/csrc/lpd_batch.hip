@@ -32,6 +32,12 @@ namespace {
 
 constexpr int kBT = 1024;  // threads per workgroup
 
+// One tiny LP on one wave.  Kept out of line (pointer arguments only), so its
+// registers do not add to those of the team and workgroup phases.
+__device__ __noinline__ void wave_solve_one(const SolveArgs* a, unsigned char* slice) {
+  lds_solve<WaveGroup>(*a, slice);
+}
+
 __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int32_t s_idx;
@@ -86,11 +92,26 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
       team_solve<kBT, 0>(it.a, w, solo, smem);
     }
   }
+
+  // ---- phase 3: one wave per tiny LP, each wave on its own LDS slice (the
+  // last phase-2 barrier guarantees nobody still reads the shared LDS).
+  const int wv = threadIdx.x / kWave;
+  if (wv < bw.wave_slots) {
+    unsigned char* slice = smem + (size_t)wv * bw.wave_slice;
+    for (;;) {
+      int32_t idx = 0;
+      if ((threadIdx.x & (kWave - 1)) == 0)
+        idx = (int32_t)atomicAdd(&bw.counters[8 * (kMaxTeamClasses + 1)], 1u);
+      idx = __builtin_amdgcn_readfirstlane(idx);
+      if (idx >= bw.n_wave) break;
+      wave_solve_one(&bw.items[bw.wave_list[idx]].a, slice);
+    }
+  }
 }
 
 __global__ void batch_clear_kernel(uint32_t* counters, BarrierSlot* slots, int nslots) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= kMaxTeamClasses) counters[i * 8] = 0u;
+  if (i <= kMaxTeamClasses + 1) counters[i * 8] = 0u;
   if (i < nslots) slots[i].epoch = 0u;
 }
 
@@ -128,10 +149,19 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   if (K.share)
     for (int32_t i = 0; i < count; ++i)
       if (wg_lds_bytes(m[i], n[i]) > limit) share_total += tableau_bytes(m[i], n[i]);
+  // Wave-per-instance slices: the whole LDS split evenly (16-byte aligned).
+  const int slots = std::max(0, std::min(K.wave_slots, kBT / kWave));
+  const size_t slice = slots > 0 ? (limit / (size_t)slots) & ~size_t(15) : 0;
+  std::vector<std::pair<double, int32_t>> wave;
   for (int32_t i = 0; i < count; ++i) {
     const double bytes = tableau_bytes(m[i], n[i]);
     work[(size_t)i] = bytes * (double)(m[i] + n[i]);  // proxy: tableau size x pivot-count scale
     const size_t lds_i = wg_lds_bytes(m[i], n[i]);
+    if (slots > 0 && lds_i <= slice) {
+      P.klass[(size_t)i] = kClassWave;
+      wave.push_back({-work[(size_t)i], i});
+      continue;
+    }
     if (lds_i <= limit) {
       P.klass[(size_t)i] = kClassLds;
       lds_wg = std::max(lds_wg, lds_i);
@@ -226,6 +256,12 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   }
   std::stable_sort(single.begin(), single.end());
   for (auto& e : single) P.single_list.push_back(e.second);
+  std::stable_sort(wave.begin(), wave.end());
+  for (auto& e : wave) P.wave_list.push_back(e.second);
+  if (!P.wave_list.empty()) {
+    P.wave_slots = slots;
+    P.wave_slice = (uint32_t)slice;
+  }
 
   // LDS: the grid walk needs the pivot row of the widest non-LDS LP plus a
   // capture list; the LDS-resident LPs need their whole tableau.
@@ -234,6 +270,7 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   P.lds_vecs = (int32_t)max_vw;
   P.cap_cap = P.ok ? (int32_t)std::min<size_t>(kCapMax, (limit - lbase) / kCapEntryBytes) : 0;
   P.lds_bytes = std::max(lds_wg, lbase + (size_t)P.cap_cap * kCapEntryBytes);
+  if (P.wave_slots > 0) P.lds_bytes = std::max(P.lds_bytes, (size_t)P.wave_slots * P.wave_slice);
 
   // Shared workspaces unless every LP brings its own.
   uint64_t team_ws_total = 0, nslots = 0;
@@ -257,7 +294,7 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   };
   P.off_items = take((uint64_t)count * sizeof(BatchItem));
   P.off_lists = take((uint64_t)count * 4 + 4);
-  P.off_counters = take(32 * (kMaxTeamClasses + 1) + 32);
+  P.off_counters = take(32 * (kMaxTeamClasses + 2) + 32);
   P.off_slots = take(nslots * sizeof(BarrierSlot));
   P.off_team_ws = take(team_ws_total);
   P.off_wg_ws = take((uint64_t)nblocks * P.wg_ws_stride);
@@ -298,6 +335,12 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
   std::copy(P.single_list.begin(), P.single_list.end(), lists + at);
   bw.single_list = dlists + at;
   bw.n_single = (int32_t)P.single_list.size();
+  at += P.single_list.size();
+  std::copy(P.wave_list.begin(), P.wave_list.end(), lists + at);
+  bw.wave_list = dlists + at;
+  bw.n_wave = (int32_t)P.wave_list.size();
+  bw.wave_slots = P.wave_slots;
+  bw.wave_slice = P.wave_slice;
   bw.counters = reinterpret_cast<uint32_t*>(base + P.off_counters);
   bw.wg_ws = P.wg_ws_stride ? base + P.off_wg_ws : nullptr;
   bw.wg_ws_stride = P.wg_ws_stride;
@@ -307,7 +350,7 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
   if (e != hipSuccess) return e;
 
   const int nslots = (int)(slots - reinterpret_cast<BarrierSlot*>(base + P.off_slots));
-  batch_clear_kernel<<<(std::max(nslots, kMaxTeamClasses + 1) + 255) / 256, 256, 0, stream>>>(
+  batch_clear_kernel<<<(std::max(nslots, kMaxTeamClasses + 2) + 255) / 256, 256, 0, stream>>>(
       bw.counters, reinterpret_cast<BarrierSlot*>(base + P.off_slots), nslots);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

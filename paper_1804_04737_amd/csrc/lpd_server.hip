@@ -277,7 +277,7 @@ void lpd_server::launch_epoch() {
     it.ws = r.dws;
     // The planner's LDS test is the one submit used; never launch an LP
     // without the workspace its class walks over.
-    if (it.klass != kClassLds && !r.has_ws) e = hipErrorInvalidValue;
+    if (it.klass != kClassLds && it.klass != kClassWave && !r.has_ws) e = hipErrorInvalidValue;
   }
   if (e == hipSuccess && P.total > meta_bytes) {
     if (meta) (void)hipFreeAsync(meta, stream);
@@ -357,6 +357,7 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   // Default threshold: any LP that could fill a team of two.
   s->knobs.team_min_bytes = s->opt.team_min_bytes != 0 ? s->opt.team_min_bytes : 2 * s->knobs.share_min_bytes_per_wg;
   s->knobs.own_workspaces = true;
+  s->knobs.wave_slots = tuned_batch_knobs().wave_slots;
   s->nslots = s->opt.max_resident;
   s->nblocks = p.multiProcessorCount;
   int lds = 0;

@@ -53,8 +53,20 @@ constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
 constexpr int kChunkSteps = 8;                 // dynamic sweep chunk: 8 x NT vectors
 constexpr int64_t kDynMinSteps = 192;          // sweeps shorter than this are all static
 
-__device__ __forceinline__ dbl2 ld_stream(const dbl2* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, p); }
+// Tableau workspaces are always device global memory.  Saying so lets the
+// compiler use global (not flat) loads and stores even where the pointer was
+// itself loaded from memory (batch descriptors).
+typedef __attribute__((address_space(1))) dbl2 gdbl2;
+__device__ __forceinline__ dbl2 ld_stream(const dbl2* p) {
+  return __builtin_nontemporal_load((const gdbl2*)p);
+}
+__device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, (gdbl2*)p); }
+// Plain loads and stores of workspace vectors, through global pointers.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ double gld(const double* p) { return *(const gdouble*)p; }
+__device__ __forceinline__ void gst(double* p, double v) { *(gdouble*)p = v; }
+__device__ __forceinline__ dbl2 gld2(const dbl2* p) { return *(const gdbl2*)p; }
+__device__ __forceinline__ void gst2(dbl2* p, dbl2 v) { *(gdbl2*)p = v; }
 
 // Grid-wide lexicographic arg-min that doubles as the barrier.
 // `c` is this workgroup's reduced candidate (identical in all its threads).
@@ -337,7 +349,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     // normalised row of the previous pivot if l was pivot row then.
     const dbl2* rowl = (l == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(w.T + (int64_t)l * ld);
     Cand pc = cand_none();
-    const double prhs = rhs_cur[l] / p;
+    const double prhs = gld(rhs_cur + l) / p;
     // Objective row after this pivot, entry v; also stages r_v in LDS.
     auto p_update = [&](int32_t v, dbl2 t, dbl2 o) -> dbl2 {
       dbl2 r, on;
@@ -348,8 +360,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       prow[v] = r;
       // Each workgroup publishes one slice of the new rows (all copies agree).
       if (v >= pub_v0 && v < pub_v1) {
-        reinterpret_cast<dbl2*>(obj_nxt)[v] = on;
-        reinterpret_cast<dbl2*>(pr_cur)[v] = r;
+        gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on);
+        gst2(reinterpret_cast<dbl2*>(pr_cur) + v, r);
       }
       price_offer(pc, on.x, 2 * (int64_t)v, ncols);
       price_offer(pc, on.y, 2 * (int64_t)v + 1, ncols);
@@ -362,8 +374,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       for (int q = 0; q < 4; ++q) {
         const int32_t v = v0 + q * NT;
         if (v < vw) {
-          t[q] = rowl[v];
-          o[q] = obj_cur[v];
+          t[q] = gld2(rowl + v);
+          o[q] = gld2(obj_cur + v);
         }
       }
 #pragma unroll
@@ -373,7 +385,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       }
     }
     if (leader && tid == 0) {
-      rhs_nxt[m] = __builtin_fma(-g, prhs, rhs_cur[m]);
+      gst(rhs_nxt + m, __builtin_fma(-g, prhs, gld(rhs_cur + m)));
       const int32_t leaving = w.basis[l];
       w.pos[leaving] = -1;
       w.pos[k] = l;
@@ -399,10 +411,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       // the static walk below.
       auto element = [&](int32_t i, int32_t v) {
         const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
-        const double f = pcol_cur[i];
+        const double f = gld(pcol_cur + i);
         const bool cap = (v == kv);
         double rh = 0.0;
-        if (cap) rh = rhs_cur[i];
+        if (cap) rh = gld(rhs_cur + i);
         const dbl2* src = (i == lprev) ? pr_prev : rowp;
         dbl2 t;
         if (i != l) t = ld_stream(src + v);
@@ -417,8 +429,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         if (cap) {
           const double an = kh ? nv.y : nv.x;
           const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
-          pcol_nxt[i] = an;
-          rhs_nxt[i] = rn;
+          gst(pcol_nxt + i, an);
+          gst(rhs_nxt + i, rn);
           const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
           if (slot < w.cap_cap) {
             cap_a[slot] = an;
@@ -439,10 +451,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
       const int64_t row_step = (int64_t)step_q * ldv;
       for (int64_t q = 0; q < n_static; ++q) {
-        const double f = pcol_cur[i];
+        const double f = gld(pcol_cur + i);
         const bool cap = (v == kv);
         double rh = 0.0;
-        if (cap) rh = rhs_cur[i];
+        if (cap) rh = gld(rhs_cur + i);
         const dbl2* src = (i == lprev) ? pr_prev : rowp;
         dbl2 t;
         if (i != l) t = ld_stream(src + v);
@@ -461,8 +473,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           // itself is formed after the sweep by the whole workgroup.
           const double an = kh ? nv.y : nv.x;
           const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
-          pcol_nxt[i] = an;
-          rhs_nxt[i] = rn;
+          gst(pcol_nxt + i, an);
+          gst(rhs_nxt + i, rn);
           const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
           if (slot < w.cap_cap) {
             cap_a[slot] = an;

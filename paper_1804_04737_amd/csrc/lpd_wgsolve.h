@@ -1,8 +1,9 @@
-// Single-workgroup solve of one small dense LP whose whole tableau fits in LDS.
+// Solve of one small dense LP whose whole tableau fits in LDS, by one
+// workgroup or by one wave.
 //
 // The (m+1) x (n+m+1) tableau of Table 1 (Coutinho et al., Section 2) is
-// built in LDS and one workgroup runs Steps 2-5 in a loop with workgroup
-// barriers only; the result leaves LDS once, at the end.  Same arithmetic
+// built in LDS and the group runs Steps 2-5 in a loop with group-level
+// synchronisation only; the result leaves LDS once, at the end.  Same arithmetic
 // contract as the grid path: IEEE division for the pivot row, one fma per
 // eliminated element, lexicographic (value, index) arg-minima.
 #pragma once
@@ -31,15 +32,49 @@ __host__ __device__ inline WgLayout wg_layout(int64_t m, int64_t n) {
   return L;
 }
 
+// Thread groups that can run the LDS solve: a whole workgroup of NT threads,
+// or one wave on its own slice of the workgroup's LDS (several small LPs per
+// workgroup, one per wave).
 template <int NT>
-__device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
+struct BlockGroup {
+  static constexpr int kThreads = NT;
+  __device__ static int rank() { return threadIdx.x; }
+  // LDS writes before, reads after.
+  __device__ static void sync() { __syncthreads(); }
+  // Arg-min over the group; also orders the LDS writes made before it.
+  __device__ static Cand reduce(Cand c, Cand* scratch) { return block_reduce(c, scratch); }
+  // Global stores before complete before those after.
+  __device__ static void order_global() { __syncthreads(); }
+};
+
+struct WaveGroup {
+  static constexpr int kThreads = kWave;
+  __device__ static int rank() { return threadIdx.x & (kWave - 1); }
+  // A wave's LDS accesses execute in order: only the compiler needs fencing.
+  __device__ static void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  __device__ static Cand reduce(Cand c, Cand*) {
+    sync();
+    return wave_reduce(c);
+  }
+  __device__ static void order_global() {
+    __builtin_amdgcn_s_waitcnt(0);
+    sync();
+  }
+};
+
+template <class Grp>
+__device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
+  constexpr int NT = Grp::kThreads;
   const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m, W = ncols + 1, R = m + 1;
   const WgLayout L = wg_layout(m, n);
   double* T = reinterpret_cast<double*>(smem + L.off_T);
   double* pcol = reinterpret_cast<double*>(smem + L.off_pcol);
   int32_t* basis = reinterpret_cast<int32_t*>(smem + L.off_basis);
   Cand* scratch = reinterpret_cast<Cand*>(smem + L.off_scratch);
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave, nw = NT / kWave;
+  const int tid = Grp::rank(), lane = tid & (kWave - 1), wave = tid / kWave, nw = NT / kWave;
 
   // Step 1: Table 1 layout, RHS in column W-1, objective row last.
   int32_t flags = 0;
@@ -64,7 +99,7 @@ __device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
   for (int32_t i = tid; i < m; i += NT) basis[i] = n + i;
   Cand fc = cand_none();
   fc.flags = flags;
-  fc = block_reduce(fc, scratch);
+  fc = Grp::reduce(fc, scratch);
 
   int32_t status = -1;
   if (fc.flags & kFlagNonFinite) status = kNumerical;
@@ -80,7 +115,7 @@ __device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
       if (!is_finite(v)) pc.flags |= kFlagNonFinite;
       if (!__builtin_isnan(v)) cand_offer(pc, v, j, 0.0);
     }
-    pc = block_reduce(pc, scratch);
+    pc = Grp::reduce(pc, scratch);
     if (pc.flags & kFlagNonFinite) { status = kNumerical; break; }
     if (pc.v >= -a.eps_d) { status = kOptimal; break; }
     if (iter == a.max_iter) { status = kIterLimit; break; }
@@ -97,7 +132,7 @@ __device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
         if (aik > a.eps_p) cand_offer(rc, r / aik, i, aik);
       }
     }
-    rc = block_reduce(rc, scratch);  // orders the pcol writes too
+    rc = Grp::reduce(rc, scratch);  // orders the pcol writes too
     if (rc.flags & kFlagNonFinite) { status = kNumerical; break; }
     if (rc.i == kNoIndex) { status = kUnbounded; break; }
     const int32_t l = rc.i;
@@ -106,7 +141,7 @@ __device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
     // Step 4: divide the pivot row by the pivot.
     double* Tl = T + (size_t)l * W;
     for (int32_t j = tid; j < W; j += NT) Tl[j] = Tl[j] / p;
-    __syncthreads();
+    Grp::sync();
 
     // Step 5: eliminate column k from every other row (objective row too).
     for (int32_t i = wave; i < R; i += nw) {
@@ -123,12 +158,12 @@ __device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
       }
     }
     ++iter;
-    __syncthreads();
+    Grp::sync();
   }
 
   // Read-out: x from the basic rows' RHS, objective value, duals.
   for (int32_t j = tid; j < n; j += NT) a.x[j] = 0.0;
-  __syncthreads();
+  Grp::order_global();
   for (int32_t i = tid; i < m; i += NT) {
     const int32_t bv = basis[i];
     if (bv < n) a.x[bv] = T[(size_t)i * W + W - 1];
@@ -142,6 +177,11 @@ __device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
     *a.status = status;
     if (a.iterations) *a.iterations = iter;
   }
+}
+
+template <int NT>
+__device__ void wg_solve(const SolveArgs& a, unsigned char* smem) {
+  lds_solve<BlockGroup<NT>>(a, smem);
 }
 
 

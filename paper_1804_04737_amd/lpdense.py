@@ -46,7 +46,8 @@ class Outputs(ctypes.Structure):
 class BatchOptions(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
                 ("team_size", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("team_min_bytes", _I64), ("iterations", _P), ("team_bytes_per_wg", _I64)]
+                ("team_min_bytes", _I64), ("iterations", _P), ("team_bytes_per_wg", _I64),
+                ("wave_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -274,13 +275,14 @@ def pack_batch(lps, device="cuda") -> PackedBatch:
 
 def solve_batch(pb: PackedBatch, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
                 team_size: int = 0, team_min_bytes: int = 0, team_bytes_per_wg: int = 0,
-                grid_blocks: int = 0, stream=None) -> PackedBatch:
+                wave_slots: int = 0, grid_blocks: int = 0, stream=None) -> PackedBatch:
     """lp_solve_batch on a PackedBatch (asynchronous; outputs land in pb)."""
     import numpy as np
     def hp(a):
         return a.ctypes.data_as(ctypes.c_void_p)
     opts = BatchOptions(float(eps_d), float(eps_p), int(max_iter), int(team_size), int(grid_blocks),
-                        int(team_min_bytes), pb.iterations.data_ptr(), int(team_bytes_per_wg))
+                        int(team_min_bytes), pb.iterations.data_ptr(), int(team_bytes_per_wg),
+                        int(wave_slots), 0)
     m = np.ascontiguousarray(pb.m, dtype=np.int64)
     n = np.ascontiguousarray(pb.n, dtype=np.int64)
     rc = load().lp_solve_batch(pb.count, hp(m), hp(n), pb.A.data_ptr(), hp(pb.A_off), pb.b.data_ptr(),

@@ -61,7 +61,33 @@ def test_batch_order_and_single_solve_agree():
         assert int(r.status.item()) == st1[p]
 
 
-def test_batch_with_edge_cases():
+def _tiny_lps(seed, count=60):
+    """Mostly tiny LPs (one wave each when wave slots are on) plus a few
+    larger ones for the other classes."""
+    rng = np.random.default_rng(seed)
+    shapes = [(int(rng.integers(1, 30)), int(rng.integers(1, 30))) for _ in range(count - 6)]
+    shapes += [(45, 50), (60, 40), (120, 90), (300, 200), (1, 200), (200, 1)]
+    return [lpgen.dense_lp(m, n, 5000 * seed + i) for i, (m, n) in enumerate(shapes)]
+
+
+@pytest.mark.parametrize("wave_slots", [2, 4, 16])
+def test_batch_wave_per_instance_equals_oracle(wave_slots):
+    """One wave per tiny LP (its tableau in the wave's LDS slice): bits equal
+    the oracle's, and equal the same batch solved with wave slots off."""
+    lps = _tiny_lps(wave_slots)
+    announce(f"batch wave_slots={wave_slots}, {len(lps)} LPs")
+    xs, obj, st, it = _run_batch(lps, wave_slots=wave_slots)
+    xs0, obj0, st0, it0 = _run_batch(lps, wave_slots=-1)
+    for i, (A, b, c) in enumerate(lps):
+        ref = oracle.solve(A, b, c)
+        assert st[i] == ref.status and it[i] == ref.iterations, i
+        assert np.array_equal(bits(xs[i]), bits(ref.x)), i
+        assert bits([obj[i]])[0] == bits([ref.obj])[0], i
+        assert np.array_equal(bits(xs[i]), bits(xs0[i])) and it[i] == it0[i]
+
+
+@pytest.mark.parametrize("wave_slots", [-1, 8])
+def test_batch_with_edge_cases(wave_slots):
     A = np.array([[1.0, 2.0], [3.0, 1.0]])
     lps = [
         (A, np.array([1.0, -2.0]), np.array([1.0, 1.0])),                          # INFEASIBLE_START
@@ -72,8 +98,8 @@ def test_batch_with_edge_cases():
         (np.array([[0.0, 1.0]]), np.array([1.0]), np.array([1.0, 1.0])),
         lpgen.dense_lp(500, 600, 4),
     ]
-    announce("batch edge cases")
-    xs, obj, st, it = _run_batch(lps, team_size=4, team_min_bytes=1_000_000)
+    announce(f"batch edge cases wave_slots={wave_slots}")
+    xs, obj, st, it = _run_batch(lps, team_size=4, team_min_bytes=1_000_000, wave_slots=wave_slots)
     for i, (A_, b_, c_) in enumerate(lps):
         ref = oracle.solve(A_, b_, c_)
         assert st[i] == ref.status and it[i] == ref.iterations
@@ -81,9 +107,9 @@ def test_batch_with_edge_cases():
 
 
 def test_batch_max_iter_applies_to_each_lp():
-    lps = _mixed_lps(3, count=12)
+    lps = _mixed_lps(3, count=12) + _tiny_lps(3, count=12)
     announce("batch max_iter=5")
-    xs, obj, st, it = _run_batch(lps, max_iter=5)
+    xs, obj, st, it = _run_batch(lps, max_iter=5, wave_slots=4)
     for i, (A, b, c) in enumerate(lps):
         ref = oracle.solve(A, b, c, max_iter=5)
         assert st[i] == ref.status and it[i] == ref.iterations
