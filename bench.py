@@ -194,24 +194,31 @@ def serve_bench(args):
     log(f"one at a time: {single_lps_s:.1f} LPs/s over {n1} requests, {b1 / el1 / 1e9:.0f} GB/s effective")
 
     sweep = []
+    n_req = len(picks)
     for rate in rates:
-        arr = lpgen.poisson_arrivals(rate, len(picks), args.seed + int(rate))
+        arr = lpgen.poisson_arrivals(rate, n_req + args.serve_warmup, args.seed + int(rate))
+        reqs = [pool[p] for p in rng.integers(0, len(pool), size=args.serve_warmup)] + [pool[p] for p in picks]
         with lpdense.Server(int(args.budget_gb * 1e9), pivots_per_epoch=args.pivots_per_epoch,
                             epoch_bytes_per_wg=int(args.epoch_mb * (1 << 20)),
-                            team_bytes_per_wg=int(args.share_kb * 1024)) as srv:
+                            team_bytes_per_wg=int(args.share_kb * 1024),
+                            max_resident=args.max_resident) as srv:
             done = []
+            ids = []
             i = 0
             t0 = time.perf_counter()
-            while len(done) < len(picks):
+            while len(done) < len(reqs):
                 now = time.perf_counter() - t0
-                while i < len(picks) and arr[i] <= now:
-                    srv.submit(*pool[picks[i]])
+                while i < len(reqs) and arr[i] <= now:
+                    ids.append(srv.submit(*reqs[i]))
                     i += 1
                 done += srv.poll()
-                wait = (arr[i] - (time.perf_counter() - t0)) if i < len(picks) else 0.0005
+                wait = (arr[i] - (time.perf_counter() - t0)) if i < len(reqs) else 0.0005
                 time.sleep(min(max(wait, 0.0), 0.0005))
             st = srv.stats()
+        # The first requests warm the server up; statistics cover the rest.
+        measured = set(ids[args.serve_warmup:])
         bad = [d for d in done if d.status != lpdense.OPTIMAL]
+        done = [d for d in done if d.id in measured]
         lat = np.array([d.latency for d in done]) * 1e3
         span = max(d.t_done for d in done) - min(d.t_arrive for d in done)
         gb = sum(alg_bytes(d.m, d.n, d.iterations) for d in done) / 1e9
@@ -227,9 +234,10 @@ def serve_bench(args):
         "metric": METRIC, "value": top["LPs_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": len(rates),
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"served: Poisson arrivals of {len(picks)} dense LPs per rate drawn from a pool of "
+        "config": {"workload": f"served: Poisson arrivals of {args.serve_warmup} warm-up + {len(picks)} timed dense "
+                               f"LPs per rate drawn from a pool of "
                                f"{len(pool)} (m, n log-uniform in [64, 4096], seed {args.seed}), footprint budget "
-                               f"{args.budget_gb:g} GB, " + (f"{args.pivots_per_epoch} pivots per LP per epoch" if args.pivots_per_epoch > 0
+                               f"{args.budget_gb:g} GB, {args.max_resident or 'default'} resident slots, " + (f"{args.pivots_per_epoch} pivots per LP per epoch" if args.pivots_per_epoch > 0
                                  else f"pivot budgets sized for {args.epoch_mb:g} MiB per workgroup per epoch"),
                    "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
                    "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
@@ -257,14 +265,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
     ap.add_argument("--workload", choices=["dense", "batch", "serve"], default="dense")
-    ap.add_argument("--serve-rates", default="100,1000,5000", help="serve: arrival rates (LPs/s)")
-    ap.add_argument("--serve-requests", type=int, default=200, help="serve: requests per rate")
+    ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates (LPs/s)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="serve: timed requests per rate")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="serve: untimed requests before them")
     ap.add_argument("--serve-pool", type=int, default=48, help="serve: distinct LPs the requests draw from")
     ap.add_argument("--serve-single", type=int, default=100, help="serve: requests timed one at a time")
     ap.add_argument("--pivots-per-epoch", type=int, default=0,
                     help="serve: pivot budget per LP per launch (0: sized per LP from --epoch-mb)")
     ap.add_argument("--epoch-mb", type=float, default=256.0,
                     help="serve: tableau MiB each workgroup streams per launch (sizes the pivot budgets)")
+    ap.add_argument("--max-resident", type=int, default=0, help="serve: resident slots (0: library default)")
     ap.add_argument("--share-kb", type=float, default=0,
                     help="serve: least tableau KiB per workgroup of a team (0: library default)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: footprint budget (1e9 bytes)")
