@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
     ap.add_argument("--workload", choices=["dense", "batch", "serve"], default="dense")
+    ap.add_argument("--schedule", choices=["auto", "condensed"], default="auto",
+                    help="dense: full tableau (auto: grid for large LPs) or the condensed tableau "
+                         "(nonbasic columns only, bitwise-identical results)")
     ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates (LPs/s)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve: timed requests per rate")
     ap.add_argument("--serve-warmup", type=int, default=100, help="serve: untimed requests before them")
@@ -322,8 +325,10 @@ def main():
         del src, dst
         log("copied 1 GiB for counter calibration")
 
+    sched = lpdense.SCHED_GRID_CONDENSED if args.schedule == "condensed" else lpdense.SCHED_AUTO
+
     def step():
-        return lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=lpdense.SCHED_AUTO,
+        return lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=sched,
                                       grid_blocks=args.grid_blocks, want_y=True, stream=stream)
 
     for w in range(args.warmup):
@@ -350,11 +355,14 @@ def main():
     total_piv = sum(pivots)
     log(f"timed {args.steps} steps in {elapsed:.3f} s; pivots per step {pivots}; event ms {ev_ms}")
 
-    R, W = m + 1, n + m + 1
+    # Algorithmic bytes of one pivot: the stored tableau read and written once
+    # (the full tableau, or only the nonbasic columns and the RHS).
+    R, W = m + 1, (n + 1 if args.schedule == "condensed" else n + m + 1)
     bytes_per_pivot = 16.0 * R * W
     avg_ms = sum(ev_ms) / len(ev_ms)
     achieved = bytes_per_pivot * (total_piv / args.steps) / (avg_ms / 1e3) / 1e9
-    traffic = counter_traffic(pivots[0]) if (m, n, args.seed) == (8192, 8192, 0) else None
+    traffic = (counter_traffic(pivots[0]) if (m, n, args.seed) == (8192, 8192, 0) and args.schedule == "auto"
+               else None)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 1)}
@@ -363,7 +371,7 @@ def main():
     if args.phases:
         K = max(pivots)
         r = lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, grid_blocks=args.grid_blocks,
-                                   phase_cap=K, stream=stream)
+                                   phase_cap=K, schedule=sched, stream=stream)
         torch.cuda.synchronize()
         it = int(r.iterations.item())
         if r.phase_ticks is not None and it > 2:
@@ -394,7 +402,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"dense LP max c^T x, Ax<=b, x>=0, m={m}, n={n}, seed {args.seed}, "
-                               f"full solve from the slack basis (Dantzig, lowest-index ties)",
+                               f"full solve from the slack basis (Dantzig, lowest-index ties)"
+                               + ("; condensed tableau (nonbasic columns only)" if args.schedule == "condensed"
+                                  else ""),
+                   "schedule": args.schedule,
                    "m": m, "n": n, "pivots_per_step": pivots[0],
                    "status": lpdense.STATUS_NAMES[statuses[0]],
                    "bytes_per_pivot": int(bytes_per_pivot),

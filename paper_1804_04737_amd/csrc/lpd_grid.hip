@@ -8,12 +8,12 @@
 namespace lpd {
 namespace {
 
-template <int NT, int MAP>
+template <int NT, int MAP, bool CD = false>
 __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   uint32_t epoch = 0;
   const Team tm{(int)blockIdx.x, (int)gridDim.x, w.slots, &epoch};
-  team_solve<NT, MAP>(a, w, tm, smem);
+  team_solve<NT, MAP, CD>(a, w, tm, smem);
 }
 
 // Clears the barrier slots of a fresh workspace (stream-ordered, no memset node).
@@ -28,6 +28,9 @@ constexpr int kNT = 1024;
 typedef void (*GridKernel)(SolveArgs, GridWork);
 constexpr GridKernel kVariants[] = {grid_solve_kernel<kNT, 0>, grid_solve_kernel<kNT, 1>};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+// Condensed tableau (nonbasic columns only).
+constexpr GridKernel kCondensed = grid_solve_kernel<kNT, 0, true>;
+
 
 // LPD_GRID_VARIANT (tuning / diagnostics) picks a kernel variant.
 // LPD_GRID_VARIANT (tuning / diagnostics) picks the thread mapping; 0 by default.
@@ -36,6 +39,8 @@ int variant_index(int64_t) {
   const int x = e ? atoi(e) : 0;
   return (x >= 0 && x < kNumVariants) ? x : 0;
 }
+
+GridKernel pick_kernel(int64_t vw, bool condensed) { return condensed ? kCondensed : kVariants[variant_index(vw)]; }
 
 int lds_limit() {
   int dev = 0, lds_max = 0;
@@ -47,8 +52,8 @@ int lds_limit() {
 // LDS plan of the grid kernel: reduction scratch, the normalised pivot row
 // (vw 16-byte vectors) and a capture list of up to kCapMax entries, shrunk to
 // what the LDS leaves.  Returns 0 if the pivot row alone does not fit.
-size_t lds_plan(int64_t m, int64_t n, int32_t* cap) {
-  const int64_t vw = (n + m + 1) / 2;
+size_t lds_plan(int64_t m, int64_t n, int32_t* cap, bool condensed) {
+  const int64_t vw = grid_layout(m, n, 1, condensed).vw;
   const size_t base = kScratchBytes + (size_t)vw * 16 + 16;
   const size_t limit = (size_t)lds_limit();
   if (base > limit) return 0;
@@ -59,20 +64,20 @@ size_t lds_plan(int64_t m, int64_t n, int32_t* cap) {
 
 }  // namespace
 
-size_t grid_lds_bytes(int64_t m, int64_t n, int /*nthreads*/) {
+size_t grid_lds_bytes(int64_t m, int64_t n, int /*nthreads*/, bool condensed) {
   int32_t cap = 0;
-  return lds_plan(m, n, &cap);
+  return lds_plan(m, n, &cap, condensed);
 }
 
-int grid_max_blocks(int64_t m, int64_t n, int nthreads) {
+int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed) {
   (void)nthreads;
   int32_t cap = 0;
-  const size_t lds = lds_plan(m, n, &cap);
+  const size_t lds = lds_plan(m, n, &cap, condensed);
   if (lds == 0) return 0;
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  auto fn = kVariants[variant_index((n + m + 1) / 2)];
+  auto fn = pick_kernel(grid_layout(m, n, 1, condensed).vw, condensed);
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0;
@@ -81,11 +86,11 @@ int grid_max_blocks(int64_t m, int64_t n, int nthreads) {
 }
 
 hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, int nthreads,
-                             hipStream_t stream) {
+                             hipStream_t stream, bool condensed) {
   (void)nthreads;
-  const GridLayout L = grid_layout(a.m, a.n, nblocks);
+  const GridLayout L = grid_layout(a.m, a.n, nblocks, condensed);
   GridWork w = make_grid_work(L, a.m, workspace);
-  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap);
+  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap, condensed);
   w.lds_vecs = (int32_t)L.vw;
   if (lds == 0) return hipErrorInvalidValue;
 
@@ -94,7 +99,7 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  auto fn = kVariants[variant_index(L.vw)];
+  auto fn = pick_kernel(L.vw, condensed);
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   SolveArgs args = a;

@@ -13,6 +13,7 @@ struct SolveState {
   int32_t k, l, lprev;
   double g, p;
   int64_t iter;
+  int32_t kc, kprev;  // condensed tableau: stored column of k; entering variable of the last pivot
 };
 
 // Inputs, options and outputs of one LP solve as the kernels see them.
@@ -67,6 +68,9 @@ struct GridWork {
   double* rhs[2];  // right-hand side, rows 0..m (row m = objective value), by parity
   int32_t* basis;  // m: basic variable of each row
   int32_t* pos;    // n+m: row of each basic variable, -1 if nonbasic
+  // Condensed tableau only (T holds the n nonbasic columns):
+  int32_t* lab;    // n: variable held by each stored column
+  int32_t* col_of; // n+m: stored column of each nonbasic variable, -1 if basic
   uint32_t* tickets;   // chunk tickets of the sweep's dynamic part: [0] and [32], by pivot parity
   BarrierSlot* slots; // 2 * nblocks
   int32_t cap_cap;     // capacity of the LDS capture list (entries)
@@ -76,15 +80,18 @@ struct GridWork {
 // Sizes of the grid workspace pieces (bytes, each rounded to 256).
 struct GridLayout {
   int64_t ld, vw;
-  uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_tickets, off_slots, total;
+  uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_lab, off_colof, off_tickets,
+      off_slots, total;
 };
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// Workspace of one team solve of an m x n LP by `nblocks` workgroups.
-__host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblocks) {
+// Workspace of one team solve of an m x n LP by `nblocks` workgroups.  The
+// full tableau stores the n+m columns of Table 1; the condensed one only the
+// n columns of the nonbasic variables (the basic ones are unit columns).
+__host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblocks, bool condensed = false) {
   GridLayout L{};
-  L.vw = (n + m + 1) / 2;
+  L.vw = condensed ? (n + 1) / 2 : (n + m + 1) / 2;
   L.ld = round_up(2 * L.vw, 32);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -99,6 +106,8 @@ __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblo
   L.off_rhs = take(2ull * (uint64_t)(m + 1) * 8);
   L.off_basis = take((uint64_t)m * 4);
   L.off_pos = take((uint64_t)(n + m) * 4);
+  L.off_lab = take(condensed ? (uint64_t)(n + 1) * 4 : 0);  // n + 1: read in pairs
+  L.off_colof = take(condensed ? (uint64_t)(n + m) * 4 : 0);
   L.off_tickets = take(256);  // two counters on separate 128 B lines
   L.off_slots = take(2ull * nblocks * sizeof(BarrierSlot));
   L.total = off;
@@ -120,6 +129,8 @@ __host__ __device__ inline GridWork make_grid_work(const GridLayout& L, int64_t 
   }
   w.basis = reinterpret_cast<int32_t*>(base + L.off_basis);
   w.pos = reinterpret_cast<int32_t*>(base + L.off_pos);
+  w.lab = reinterpret_cast<int32_t*>(base + L.off_lab);
+  w.col_of = reinterpret_cast<int32_t*>(base + L.off_colof);
   w.tickets = reinterpret_cast<uint32_t*>(base + L.off_tickets);
   w.slots = reinterpret_cast<BarrierSlot*>(base + L.off_slots);
   return w;
@@ -127,12 +138,12 @@ __host__ __device__ inline GridWork make_grid_work(const GridLayout& L, int64_t 
 
 // Host-side launchers (return hipError_t of the launch).
 hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, int nthreads,
-                             hipStream_t stream);
+                             hipStream_t stream, bool condensed = false);
 // Largest grid the persistent kernel can run co-resident with `nthreads` per block
 // and the LDS a given tableau width needs (0 if it cannot run at all).
-int grid_max_blocks(int64_t m, int64_t n, int nthreads);
+int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed = false);
 // LDS bytes the grid kernel needs for an n+m wide tableau.
-size_t grid_lds_bytes(int64_t m, int64_t n, int nthreads);
+size_t grid_lds_bytes(int64_t m, int64_t n, int nthreads, bool condensed = false);
 
 // Single-workgroup solve with the tableau resident in LDS.
 size_t wg_lds_bytes(int64_t m, int64_t n);

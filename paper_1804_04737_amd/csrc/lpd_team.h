@@ -162,6 +162,15 @@ __device__ __forceinline__ void price_offer(Cand& c, double v, int64_t j, int64_
   }
 }
 
+// Condensed tableau: stored column `col` holds variable `label`; ties are
+// broken by the label (as on the full tableau), the column is the payload.
+__device__ __forceinline__ void price_offer_cd(Cand& c, double v, int32_t label, int32_t col, int32_t sc) {
+  if (col < sc) {
+    if (!is_finite(v)) c.flags |= kFlagNonFinite;
+    if (!__builtin_isnan(v)) cand_offer(c, v, label, (double)col);
+  }
+}
+
 // Ratio-test contribution of row i with new entering-column value `a` and
 // new right-hand side `r` (Step 3 of the next pivot).
 __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t i, double eps_p) {
@@ -173,7 +182,14 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 //   0: workgroup b owns NT consecutive vectors per sweep step;
 //   1: each workgroup is split into NT/256 sub-groups of 256 threads that act
 //      as workgroups b, b + nb, b + 2 nb, ... (4 KiB pieces per sweep step).
-template <int NT, int MAP>
+// CD selects the condensed tableau: T holds only the n columns of the
+// nonbasic variables (lab[c]: variable of stored column c).  A pivot on
+// (l, k) turns k's column into the leaving variable's: its entries are what
+// the full tableau computes for the unit column e_l, fma(-f_i, RN(1/p), +0)
+// and RN(1/p) in row l, so every value equals the full tableau's bit for bit.
+// basis[l] changes one pivot late (all workgroups read basis[] while the
+// leader would otherwise write it): the row of the previous pivot holds kprev.
+template <int NT, int MAP, bool CD = false>
 __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm, unsigned char* smem) {
   Cand* scratch = reinterpret_cast<Cand*>(smem);
   dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
@@ -189,6 +205,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const int nb = tm.size, tid = threadIdx.x;
   const bool leader = tm.rank == 0;
   const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m;
+  const int32_t sc = CD ? n : ncols;  // stored (priced) columns
   const int64_t ld = w.ld;
   const int32_t vw = (int32_t)w.vw;
   const int64_t G = (int64_t)nb * NT;
@@ -222,6 +239,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   int32_t lprev = -1;  // pivot row of the last pivot done (-1: none)
   int32_t fpar = 0;    // parity of the current objective / rhs buffers
   int32_t k = -1, l = -1;
+  int32_t kc = -1, kprev = -1;  // stored column of k; k of the previous pivot
   double g = 0.0, p = 1.0;
   // A resumable solve that was suspended between pivots picks up where it
   // stopped: the tableau and vectors are in the workspace, the scalars here.
@@ -233,6 +251,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     g = a.state->g;
     p = a.state->p;
     iter = a.state->iter;
+    kc = a.state->kc;
+    kprev = a.state->kprev;
     fpar = (int32_t)(iter & 1);
   } else {
     // ---------------- Step 1: initial tableau (Table 1) ----------------
@@ -243,8 +263,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         const int32_t j0 = 2 * v, j1 = 2 * v + 1;
         const double* Ai = a.A + (int64_t)i * n;
         dbl2 t;
-        t.x = j0 < n ? Ai[j0] : (j0 == n + i ? 1.0 : 0.0);
-        t.y = j1 < n ? Ai[j1] : (j1 == n + i ? 1.0 : 0.0);
+        t.x = j0 < n ? Ai[j0] : (!CD && j0 == n + i ? 1.0 : 0.0);
+        t.y = j1 < n ? Ai[j1] : (!CD && j1 == n + i ? 1.0 : 0.0);
         if (!is_finite(t.x) || !is_finite(t.y)) flags |= kFlagNonFinite;
         st_stream(reinterpret_cast<dbl2*>(w.T + (int64_t)i * ld) + v, t);
         v += step_r;
@@ -270,7 +290,13 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       }
       w.rhs[0][i] = bi;
     }
-    for (int64_t j = gid; j < ncols; j += G) w.pos[j] = j < n ? -1 : (int32_t)(j - n);
+    for (int64_t j = gid; j < ncols; j += G) {
+      w.pos[j] = j < n ? -1 : (int32_t)(j - n);
+      if (CD) {
+        w.col_of[j] = j < n ? (int32_t)j : -1;
+        if (j < n) w.lab[j] = (int32_t)j;
+      }
+    }
 
     // Zeroed whatever the team size: a resumable solve may be continued by a
     // larger team in a later launch.
@@ -294,21 +320,23 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       const dbl2* o = reinterpret_cast<const dbl2*>(w.obj[0]);
       for (int32_t v = tid; v < vw; v += NT) {
         const dbl2 ov = o[v];
-        price_offer(pc, ov.x, 2 * (int64_t)v, ncols);
-        price_offer(pc, ov.y, 2 * (int64_t)v + 1, ncols);
+        // Stored column c holds variable c before the first pivot.
+        price_offer(pc, ov.x, 2 * (int64_t)v, sc);
+        price_offer(pc, ov.y, 2 * (int64_t)v + 1, sc);
       }
       pc = block_reduce(pc, scratch);
       if (pc.flags & kFlagNonFinite) status = kNumerical;
       else if (pc.v >= -a.eps_d) status = kOptimal;
       else if (a.max_iter == 0) status = kIterLimit;
       k = pc.i;
+      kc = pc.i;
       g = pc.v;
     }
     // ---------------- Step 3 on the initial tableau ----------------
     if (status < 0) {
       Cand rc = cand_none();
       for (int64_t i = gid; i < m; i += G) {
-        const double aik = w.T[i * ld + k];
+        const double aik = w.T[i * ld + kc];
         const double r = w.rhs[0][i];
         w.pcol[0][i] = aik;
         ratio_offer(rc, aik, r, (int32_t)i, a.eps_p);
@@ -350,21 +378,38 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     const dbl2* rowl = (l == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(w.T + (int64_t)l * ld);
     Cand pc = cand_none();
     const double prhs = gld(rhs_cur + l) / p;
+    // Condensed: the variable leaving the basis (row l), which takes over
+    // stored column kc.
+    const int32_t vleave = CD ? ((l == lprev) ? kprev : w.basis[l]) : 0;
     // Objective row after this pivot, entry v; also stages r_v in LDS.
     auto p_update = [&](int32_t v, dbl2 t, dbl2 o) -> dbl2 {
       dbl2 r, on;
-      r.x = t.x / p;
-      r.y = t.y / p;
-      on.x = __builtin_fma(-g, r.x, o.x);
-      on.y = __builtin_fma(-g, r.y, o.y);
+      if constexpr (CD) {
+        const bool x_k = 2 * v == kc, y_k = 2 * v + 1 == kc;
+        r.x = x_k ? 1.0 / p : t.x / p;
+        r.y = y_k ? 1.0 / p : t.y / p;
+        on.x = __builtin_fma(-g, r.x, x_k ? 0.0 : o.x);
+        on.y = __builtin_fma(-g, r.y, y_k ? 0.0 : o.y);
+      } else {
+        r.x = t.x / p;
+        r.y = t.y / p;
+        on.x = __builtin_fma(-g, r.x, o.x);
+        on.y = __builtin_fma(-g, r.y, o.y);
+      }
       prow[v] = r;
       // Each workgroup publishes one slice of the new rows (all copies agree).
       if (v >= pub_v0 && v < pub_v1) {
         gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on);
         gst2(reinterpret_cast<dbl2*>(pr_cur) + v, r);
       }
-      price_offer(pc, on.x, 2 * (int64_t)v, ncols);
-      price_offer(pc, on.y, 2 * (int64_t)v + 1, ncols);
+      if constexpr (CD) {
+        const int2 lb = *reinterpret_cast<const int2*>(w.lab + 2 * v);
+        price_offer_cd(pc, on.x, 2 * v == kc ? vleave : lb.x, 2 * v, sc);
+        price_offer_cd(pc, on.y, 2 * v + 1 == kc ? vleave : lb.y, 2 * v + 1, sc);
+      } else {
+        price_offer(pc, on.x, 2 * (int64_t)v, ncols);
+        price_offer(pc, on.y, 2 * (int64_t)v + 1, ncols);
+      }
       return on;
     };
     const dbl2* obj_cur = reinterpret_cast<const dbl2*>(w.obj[cur]);
@@ -386,10 +431,19 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     }
     if (leader && tid == 0) {
       gst(rhs_nxt + m, __builtin_fma(-g, prhs, gld(rhs_cur + m)));
-      const int32_t leaving = w.basis[l];
-      w.pos[leaving] = -1;
-      w.pos[k] = l;
-      w.basis[l] = k;
+      if constexpr (CD) {
+        if (lprev >= 0) w.basis[lprev] = kprev;  // the previous pivot's change, one pivot late
+        w.pos[vleave] = -1;
+        w.pos[k] = l;
+        w.lab[kc] = vleave;
+        w.col_of[vleave] = kc;
+        w.col_of[k] = -1;
+      } else {
+        const int32_t leaving = w.basis[l];
+        w.pos[leaving] = -1;
+        w.pos[k] = l;
+        w.basis[l] = k;
+      }
       if (iter < a.trace_cap && a.trace) {
         a.trace[2 * iter] = k;
         a.trace[2 * iter + 1] = l;
@@ -397,14 +451,18 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     }
     pc = block_reduce(pc, scratch);  // also orders the LDS writes of prow
     if (tk && tid == 0) tk[1] = __builtin_amdgcn_s_memrealtime();
-    const int32_t kn = pc.i;
+    const int32_t kn = pc.i;                                  // entering variable of the next pivot
+    const int32_t kcn = CD ? (int32_t)pc.aux : pc.i;          // ... and its stored column
     const double gn = pc.v;
     const int32_t pflags = pc.flags;
 
     // ---- Q_t: Step 5 on every constraint row, fused with Step 3 for k_{t+1}.
     Cand rc = cand_none();
     {
-      const int32_t kv = kn >> 1, kh = kn & 1;
+      const int32_t kv = kcn >> 1, kh = kcn & 1;
+      // Condensed: stored column kc becomes the leaving variable's column,
+      // whose full-tableau entries before the pivot are 0 off row l.
+      const int32_t kcv = kc >> 1, kch = kc & 1;
       const double eps_p = a.eps_p;
       const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
       // One element (i, v) of the dynamic part: the same work as one step of
@@ -418,6 +476,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         const dbl2* src = (i == lprev) ? pr_prev : rowp;
         dbl2 t;
         if (i != l) t = ld_stream(src + v);
+        if (CD && v == kcv) {
+          if (kch) t.y = 0.0;
+          else t.x = 0.0;
+        }
         const dbl2 r = prow[v];
         dbl2 nv;
         if (i == l) {
@@ -458,6 +520,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         const dbl2* src = (i == lprev) ? pr_prev : rowp;
         dbl2 t;
         if (i != l) t = ld_stream(src + v);
+        if (CD && v == kcv) {
+          if (kch) t.y = 0.0;
+          else t.x = 0.0;
+        }
         const dbl2 r = prow[v];
         dbl2 nv;
         if (i == l) {
@@ -531,6 +597,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     // ---- loop control (identical decision in every workgroup)
     ++iter;
     lprev = l;
+    kprev = k;
     fpar = (int)(iter & 1);
     if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
     else if (pflags & kFlagNonFinite) status = kNumerical;
@@ -539,6 +606,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     else if (gr.flags & kFlagNonFinite) status = kNumerical;
     else if (gr.i == kNoIndex) status = kUnbounded;
     k = kn;
+    kc = kcn;
     g = gn;
     l = gr.i;
     p = gr.aux;
@@ -548,8 +616,11 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     // Suspended: keep the scalars for the next call (all workgroups agree).
     if (leader && tid == 0)
       __hip_atomic_store(w.tickets + 32 * ((iter + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (CD && leader && tid == 0 && lprev >= 0) w.basis[lprev] = kprev;
     if (leader && tid == 0) {
       a.state->phase = 1;
+      a.state->kc = kc;
+      a.state->kprev = kprev;
       a.state->k = k;
       a.state->l = l;
       a.state->lprev = lprev;
@@ -570,18 +641,24 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     a.x[j] = r >= 0 ? rhs_f[r] : 0.0;
   }
   if (a.y)
-    for (int64_t i = gid; i < m; i += G) a.y[i] = obj_f[n + i];
+    for (int64_t i = gid; i < m; i += G) {
+      // A basic variable's objective-row entry is +0 in the full tableau.
+      const int32_t col = CD ? w.col_of[n + i] : (int32_t)(n + i);
+      a.y[i] = col >= 0 ? obj_f[col] : 0.0;
+    }
   if (a.basis_out)
-    for (int64_t i = gid; i < m; i += G) a.basis_out[i] = w.basis[i];
+    for (int64_t i = gid; i < m; i += G) a.basis_out[i] = (CD && i == lprev) ? kprev : w.basis[i];
   if (a.tableau_out) {
     const int64_t W = (int64_t)ncols + 1;
     for (int64_t e = gid; e < (int64_t)(m + 1) * W; e += G) {
       const int64_t i = e / W, j = e - i * W;
       double val;
+      const int32_t col = (!CD || j == ncols) ? (int32_t)j : w.col_of[j];
       if (j == ncols) val = rhs_f[i];
-      else if (i == m) val = obj_f[j];
-      else if (i == lprev) val = pr_last[j];
-      else val = w.T[i * ld + j];
+      else if (col < 0) val = (i == w.pos[j]) ? 1.0 : 0.0;  // basic: unit column
+      else if (i == m) val = obj_f[col];
+      else if (i == lprev) val = pr_last[col];
+      else val = w.T[i * ld + col];
       a.tableau_out[e] = val;
     }
   }

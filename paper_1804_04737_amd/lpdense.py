@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "liblpdense.so")
 OPTIMAL, UNBOUNDED, ITERATION_LIMIT, INFEASIBLE_START, NUMERICAL, DEVICE_TIMEOUT = range(6)
 STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "NUMERICAL",
                 "DEVICE_TIMEOUT")
-SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID = 0, 1, 2
+SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED = 0, 1, 2, 3
 
 # Exported symbols, as declared in include/lpdense.h.
 EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lpd_server_create",

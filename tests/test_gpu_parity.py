@@ -16,7 +16,8 @@ from tests.gpu_util import announce, assert_bitwise_equal, bits, gpu_solve
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
-WG, GRID = lpdense.SCHED_WORKGROUP, lpdense.SCHED_GRID
+WG, GRID, CD = lpdense.SCHED_WORKGROUP, lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED
+GRIDS = pytest.mark.parametrize("schedule", [GRID, CD], ids=["grid", "condensed"])
 
 
 def _examples():
@@ -24,7 +25,7 @@ def _examples():
         return json.load(f)["examples"]
 
 
-@pytest.mark.parametrize("schedule", [WG, GRID], ids=["wg", "grid"])
+@pytest.mark.parametrize("schedule", [WG, GRID, CD], ids=["wg", "grid", "condensed"])
 @pytest.mark.parametrize("ex", _examples(), ids=lambda e: e["id"])
 def test_worked_examples(ex, schedule):
     A, b, c = (np.array(ex[k], float) for k in ("A", "b", "c"))
@@ -47,11 +48,12 @@ def test_config0_64x64_workgroup(seed):
     assert_bitwise_equal(g, ref, check_tableau=True)
 
 
+@GRIDS
 @pytest.mark.parametrize("seed", range(20))
-def test_config0_64x64_grid(seed):
+def test_config0_64x64_grid(seed, schedule):
     A, b, c = lpgen.dense_lp(64, 64, seed)
-    announce(f"64x64 seed={seed} grid schedule")
-    g = gpu_solve(A, b, c, schedule=GRID, want_tableau=True)
+    announce(f"64x64 seed={seed} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, want_tableau=True)
     ref = oracle.solve(A, b, c, want_tableau=True)
     assert_bitwise_equal(g, ref, check_tableau=True)
 
@@ -60,37 +62,41 @@ RAGGED = [(1, 1), (1, 9), (9, 1), (2, 3), (3, 300), (300, 3), (33, 65), (129, 25
           (500, 333), (333, 500), (640, 1281), (1000, 700), (31, 2049)]
 
 
+@GRIDS
 @pytest.mark.parametrize("m,n", RAGGED)
-def test_ragged_shapes_grid(m, n):
+def test_ragged_shapes_grid(m, n, schedule):
     """Shapes spanning several grid-stride sweeps with ragged row / vector tails."""
     A, b, c = lpgen.dense_lp(m, n, 7 + m + n)
-    announce(f"ragged {m}x{n} grid")
-    g = gpu_solve(A, b, c, schedule=GRID, want_tableau=m * n <= 400_000)
+    announce(f"ragged {m}x{n} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, want_tableau=m * n <= 400_000)
     ref = oracle.solve(A, b, c, want_tableau=m * n <= 400_000)
     assert_bitwise_equal(g, ref, check_tableau=m * n <= 400_000)
 
 
+@GRIDS
 @pytest.mark.parametrize("m,n,K", [(200, 300, 7), (700, 500, 23), (1025, 1023, 40)])
-def test_tableau_after_k_pivots(m, n, K):
-    """max_iter = K stops after K pivots; the whole tableau then matches."""
+def test_tableau_after_k_pivots(m, n, K, schedule):
+    """max_iter = K stops after K pivots; the whole tableau then matches (the
+    condensed schedule rebuilds the full tableau from its nonbasic columns)."""
     A, b, c = lpgen.dense_lp(m, n, 100 + K)
-    announce(f"tableau after {K} pivots {m}x{n}")
-    g = gpu_solve(A, b, c, schedule=GRID, max_iter=K, want_tableau=True)
+    announce(f"tableau after {K} pivots {m}x{n} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, max_iter=K, want_tableau=True)
     ref = oracle.solve(A, b, c, max_iter=K, want_tableau=True)
     assert_bitwise_equal(g, ref, check_tableau=True)
 
 
+@GRIDS
 @pytest.mark.parametrize("blocks", [1, 2, 3, 7, 64, 255, 0])
-def test_grid_size_invariance(blocks):
+def test_grid_size_invariance(blocks, schedule):
     """Any grid size gives the same bits (a race would show up as a difference)."""
     A, b, c = lpgen.dense_lp(300, 451, 5)
-    announce(f"grid blocks={blocks} 300x451")
-    g = gpu_solve(A, b, c, schedule=GRID, grid_blocks=blocks, want_tableau=True)
+    announce(f"grid blocks={blocks} 300x451 schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, grid_blocks=blocks, want_tableau=True)
     ref = oracle.solve(A, b, c, want_tableau=True)
     assert_bitwise_equal(g, ref, check_tableau=True)
 
 
-@pytest.mark.parametrize("schedule", [WG, GRID], ids=["wg", "grid"])
+@pytest.mark.parametrize("schedule", [WG, GRID, CD], ids=["wg", "grid", "condensed"])
 def test_edge_cases(schedule):
     A = np.array([[1.0, 2.0], [3.0, 1.0]])
     cases = {
@@ -114,7 +120,9 @@ def test_workgroup_and_grid_agree_and_errors():
     announce("wg vs grid 40x50")
     g1 = gpu_solve(A, b, c, schedule=WG, want_tableau=True)
     g2 = gpu_solve(A, b, c, schedule=GRID, want_tableau=True)
+    g3 = gpu_solve(A, b, c, schedule=CD, want_tableau=True)
     assert np.array_equal(bits(g1.tableau), bits(g2.tableau))
+    assert np.array_equal(bits(g1.tableau), bits(g3.tableau))
     import torch
     tA = torch.zeros((400, 400), dtype=torch.float64, device="cuda")
     tb = torch.ones(400, dtype=torch.float64, device="cuda")
@@ -124,11 +132,12 @@ def test_workgroup_and_grid_agree_and_errors():
     assert e.value.code == -7
 
 
+@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, CD], ids=["auto", "condensed"])
 @pytest.mark.parametrize("m,n,seed", [(1024, 1024, 0), (2048, 512, 1), (512, 2048, 2)])
-def test_medium_full_solve(m, n, seed):
+def test_medium_full_solve(m, n, seed, schedule):
     A, b, c = lpgen.dense_lp(m, n, seed)
-    announce(f"medium full solve {m}x{n}")
-    g = gpu_solve(A, b, c)
+    announce(f"medium full solve {m}x{n} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule)
     ref = oracle.solve(A, b, c)
     assert_bitwise_equal(g, ref)
     rp, rd, gap = lp_checks.residuals(A, b, c, g.x, g.y)
