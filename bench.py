@@ -82,6 +82,16 @@ def counter_traffic(pivots_per_launch: int):
     return (d["fetch_size_kib"] * d["fetch_scale"] + d["write_size_kib"] * d["write_scale"]) * 1024.0
 
 
+def single_schedule(m, n, full_tableau):
+    """Best one-LP schedule for a comparison against batching: the LDS
+    workgroup when the tableau fits in LDS, else the grid on the tableau form
+    the batch uses."""
+    from paper_1804_04737_amd import lpdense
+    if lpdense.workspace_bytes(m, n) == 0 or full_tableau:
+        return lpdense.SCHED_AUTO
+    return lpdense.SCHED_GRID_CONDENSED
+
+
 def batch_bench(args):
     """Batched workload: one lp_solve_batch call on 1024 LPs with m, n
     log-uniform in [32, 1024] (seed 0) per step, against solving the same
@@ -96,7 +106,7 @@ def batch_bench(args):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     kw = dict(team_size=args.team_size, team_min_bytes=args.team_min_bytes, wave_slots=args.wave_slots,
-              stream=stream)
+              full_tableau=args.full_tableau, stream=stream)
     for _ in range(args.warmup):
         lpdense.solve_batch(pb, **kw)
     torch.cuda.synchronize()
@@ -108,7 +118,7 @@ def batch_bench(args):
     piv = pb.iterations.cpu().numpy()
     st = pb.status.cpu().numpy()
     R = pb.m + 1
-    W = pb.n + pb.m + 1
+    W = pb.n + pb.m + 1 if args.full_tableau else pb.n + 1  # stored columns + RHS
     bytes_step = float(np.sum(piv * 16.0 * R * W))
     lps_s = args.batch_count * args.steps / el
     log(f"batched: {el * 1e3 / args.steps:.2f} ms/step, {lps_s:.1f} LPs/s, statuses {np.bincount(st)}")
@@ -118,12 +128,15 @@ def batch_bench(args):
         m, n = int(pb.m[i]), int(pb.n[i])
         a0, b0, c0 = int(pb.A_off[i]), int(pb.b_off[i]), int(pb.c_off[i])
         views.append((pb.A[a0:a0 + m * n].view(m, n), pb.b[b0:b0 + m], pb.c[c0:c0 + n]))
-    for v in views[:8]:
-        lpdense.solve_dense_ex(*v, want_y=False, stream=stream)
+    # Each LP on its best single-LP schedule: LDS workgroup if it fits, else the
+    # grid on the same tableau form as the batch.
+    scheds = [single_schedule(int(pb.m[i]), int(pb.n[i]), args.full_tableau) for i in range(pb.count)]
+    for v, sc in list(zip(views, scheds))[:8]:
+        lpdense.solve_dense_ex(*v, want_y=False, schedule=sc, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for v in views:
-        lpdense.solve_dense_ex(*v, want_y=False, stream=stream)
+    for v, sc in zip(views, scheds):
+        lpdense.solve_dense_ex(*v, want_y=False, schedule=sc, stream=stream)
     torch.cuda.synchronize()
     el1 = time.perf_counter() - t0
     single_lps_s = pb.count / el1
@@ -141,7 +154,7 @@ def batch_bench(args):
                    "one_at_a_time_effective_GBps": round(bytes_step / el1 / 1e9, 1),
                    "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
                    "team_size": args.team_size, "team_min_bytes": args.team_min_bytes,
-                   "wave_slots": args.wave_slots},
+                   "wave_slots": args.wave_slots, "tableau": "full" if args.full_tableau else "condensed"},
     }
     print(json.dumps(out), flush=True)
 
@@ -175,10 +188,11 @@ def serve_bench(args):
     stream = torch.cuda.current_stream()
     def one(lp):
         A, b, c = (torch.from_numpy(v).to(dev, non_blocking=False) for v in lp)
-        r = lpdense.solve_dense_ex(A, b, c, want_y=False, stream=stream)
+        sc = single_schedule(A.shape[0], A.shape[1], args.full_tableau)
+        r = lpdense.solve_dense_ex(A, b, c, want_y=False, schedule=sc, stream=stream)
         return r.x.cpu(), int(r.iterations.item())
     def alg_bytes(m, n, piv):
-        return 16.0 * (m + 1) * (n + m + 1) * piv
+        return 16.0 * (m + 1) * ((n + m + 1) if args.full_tableau else (n + 1)) * piv
     for q in range(min(3, len(pool))):
         one(pool[picks[q]])
     torch.cuda.synchronize()
@@ -201,7 +215,7 @@ def serve_bench(args):
         with lpdense.Server(int(args.budget_gb * 1e9), pivots_per_epoch=args.pivots_per_epoch,
                             epoch_bytes_per_wg=int(args.epoch_mb * (1 << 20)),
                             team_bytes_per_wg=int(args.share_kb * 1024),
-                            max_resident=args.max_resident) as srv:
+                            max_resident=args.max_resident, full_tableau=args.full_tableau) as srv:
             done = []
             ids = []
             i = 0
@@ -239,6 +253,7 @@ def serve_bench(args):
                                f"{len(pool)} (m, n log-uniform in [64, 4096], seed {args.seed}), footprint budget "
                                f"{args.budget_gb:g} GB, {args.max_resident or 'default'} resident slots, " + (f"{args.pivots_per_epoch} pivots per LP per epoch" if args.pivots_per_epoch > 0
                                  else f"pivot budgets sized for {args.epoch_mb:g} MiB per workgroup per epoch"),
+                   "tableau": "full" if args.full_tableau else "condensed",
                    "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
                    "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
                    "one_at_a_time_effective_GBps": round(b1 / el1 / 1e9, 1),
@@ -285,6 +300,8 @@ def main():
     ap.add_argument("--batch-lo", type=int, default=32, help="batch: smallest m and n")
     ap.add_argument("--batch-hi", type=int, default=1024, help="batch: largest m and n")
     ap.add_argument("--wave-slots", type=int, default=0, help="batch: wave-per-instance slots (0: autotune table)")
+    ap.add_argument("--full-tableau", action="store_true",
+                    help="batch / serve: grid walks on the full tableau instead of the condensed one")
     ap.add_argument("--team-size", type=int, default=0, help="batch: workgroups per team (0: autotune table)")
     ap.add_argument("--team-min-bytes", type=int, default=0, help="batch: team threshold (0: autotune table)")
     args = ap.parse_args()

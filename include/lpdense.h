@@ -175,7 +175,9 @@ typedef struct lpd_batch_options {
                                 many slices (<= 16) and an LP whose LDS tableau fits in one
                                 slice is solved by a single wave (0: autotune table, whose
                                 built-in default is off; < 0: off) */
-    int32_t reserved;
+    int32_t full_tableau;    /* 0: LPs solved by a grid walk (team or one workgroup) store
+                                the condensed tableau (LPD_SCHED_GRID_CONDENSED: the same
+                                bits, fewer bytes per pivot); nonzero: the full tableau */
 } lpd_batch_options;
 
 /*
@@ -224,8 +226,9 @@ int lp_solve_batch(int32_t count, const int64_t *m, const int64_t *n, const doub
  * stream and join the next epoch.
  *
  * Footprint of an m x n request: every device byte it holds while resident,
- * the tableau workspace (8 (m+1)(n+m+1) bytes, rows padded to 32 doubles)
- * plus a copy of A, b, c and x.  LPs whose tableau fits in LDS need no
+ * the tableau workspace (8 (m+1)(n+1) bytes on the condensed tableau,
+ * 8 (m+1)(n+m+1) on the full one, rows padded to 32 doubles) plus a copy of
+ * A, b, c and x.  LPs whose tableau fits in LDS need no
  * tableau workspace.
  */
 typedef struct lpd_server lpd_server;
@@ -239,7 +242,7 @@ typedef struct lpd_server_options {
                                   per LP so that every workgroup streams about
                                   epoch_bytes_per_wg tableau bytes per launch */
     int32_t max_resident;      /* most LPs resident at once (<= 0: 4096) */
-    int32_t reserved;
+    int32_t full_tableau;      /* as lpd_batch_options (0: condensed tableau) */
     int64_t team_min_bytes;    /* tableau bytes from which an LP may get a team
                                   (0: twice team_bytes_per_wg; < 0: never) */
     int64_t team_bytes_per_wg; /* least tableau bytes per workgroup of a team (<= 0:

@@ -254,6 +254,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
   double eps_d = LPD_DEFAULT_EPS, eps_p = LPD_DEFAULT_EPS;
   int64_t max_iter = -1, team_min = 0, per_wg = 0;
   int team_size = 0, nblocks = dev.ncu, wave_slots = 0;
+  bool condensed = true;
   int64_t* iterations = nullptr;
   if (opt) {
     if (std::isnan(opt->eps_d) || std::isnan(opt->eps_p) || std::isinf(opt->eps_d) || std::isinf(opt->eps_p))
@@ -270,6 +271,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     iterations = opt->iterations;
     if (opt->wave_slots > 16) return LPD_ERR_INVALID_ARG;
     wave_slots = opt->wave_slots;
+    condensed = opt->full_tableau == 0;
   }
   // Unset knobs (0) come from the autotune table.  A team size > 0 fixes the
   // size; else a given team_bytes_per_wg asks for per-LP sizing; else the
@@ -286,10 +288,11 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
   }
   knobs.team_min_bytes = team_min != 0 ? team_min : tuning().team_min_bytes;
   knobs.wave_slots = wave_slots > 0 ? wave_slots : (wave_slots < 0 ? 0 : tuning().wave_slots);
+  knobs.condensed = condensed;
 
   BatchPlan P = plan_batch(count, m, n, knobs, nblocks);
   if (!P.ok) return LPD_ERR_TOO_LARGE;
-  const int maxb = batch_max_blocks(P.lds_bytes);
+  const int maxb = batch_max_blocks(P.lds_bytes, P.condensed);
   if (maxb <= 0) return LPD_ERR_TOO_LARGE;
   if (nblocks > maxb) P = plan_batch(count, m, n, knobs, maxb);
 

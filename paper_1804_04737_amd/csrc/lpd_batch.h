@@ -68,6 +68,8 @@ struct BatchKnobs {
   // Wave-per-instance: > 0 splits each workgroup's LDS into this many slices;
   // an LP whose LDS tableau fits in one slice is solved by a single wave.
   int wave_slots = 0;
+  // Large LPs on the condensed tableau (nonbasic columns only; same bits).
+  bool condensed = false;
 };
 
 // Host plan: classes, queue orders, LDS and workspace sizes.
@@ -83,6 +85,7 @@ struct BatchPlan {
   std::vector<int32_t> klass, tclass, single_list, wave_list;
   int32_t wave_slots = 0;
   uint32_t wave_slice = 0;
+  bool condensed = false;
   uint64_t wg_ws_stride = 0;
   uint64_t off_items = 0, off_lists = 0, off_counters = 0, off_slots = 0, off_team_ws = 0, off_wg_ws = 0;
   uint64_t total = 0;
@@ -95,10 +98,15 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
 // / tclass must come from the plan).
 hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items, void* workspace,
                         hipStream_t stream);
-int batch_max_blocks(size_t lds_bytes);
+int batch_max_blocks(size_t lds_bytes, bool condensed = false);
 // Knobs from the autotune table (built-in defaults when there is none).
 BatchKnobs tuned_batch_knobs();
 // Tableau bytes of an m x n LP and the bytes one grid-walk workspace needs.
 inline double tableau_bytes(int64_t m, int64_t n) { return ((double)m + 1) * (double)(n + m + 1) * 8.0; }
+// Bytes of the tableau a grid walk stores and streams: the full one, or only
+// the n nonbasic columns on the condensed tableau.
+inline double stored_bytes(int64_t m, int64_t n, bool condensed) {
+  return ((double)m + 1) * (double)(condensed ? n + 1 : n + m + 1) * 8.0;
+}
 
 }  // namespace lpd

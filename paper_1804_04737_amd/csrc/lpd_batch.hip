@@ -38,6 +38,7 @@ __device__ __noinline__ void wave_solve_one(const SolveArgs* a, unsigned char* s
   lds_solve<WaveGroup>(*a, slice);
 }
 
+template <bool CD>
 __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int32_t s_idx;
@@ -66,10 +67,10 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
       if ((got.flags & kFlagTimeout) || idx >= tc.n_items) break;
       const BatchItem& it = bw.items[tc.list[idx]];
       unsigned char* ws = it.ws ? it.ws : tc.ws + (size_t)team * tc.ws_stride;
-      GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, tc.size), it.a.m, ws);
+      GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, tc.size, CD), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
-      team_solve<kBT, 0>(it.a, w, tm, smem);
+      team_solve<kBT, 0, CD>(it.a, w, tm, smem);
     }
   }
 
@@ -86,10 +87,10 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
       wg_solve<kBT>(it.a, smem);
     } else {
       unsigned char* ws = it.ws ? it.ws : bw.wg_ws + (size_t)b * bw.wg_ws_stride;
-      GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, 1), it.a.m, ws);
+      GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, 1, CD), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
-      team_solve<kBT, 0>(it.a, w, solo, smem);
+      team_solve<kBT, 0, CD>(it.a, w, solo, smem);
     }
   }
 
@@ -134,6 +135,8 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
                      size_t lds_per_block) {
   BatchPlan P;
   P.nblocks = nblocks;
+  P.condensed = K.condensed;
+  const bool cd = K.condensed;
   // Static LDS of the kernel (s_idx) plus alignment slack stays outside the dynamic budget.
   const int lds_total = lds_per_block ? (int)lds_per_block : lds_limit_bytes();
   const size_t limit = (size_t)std::max(0, lds_total - 256);
@@ -148,13 +151,13 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   double share_total = 0.0;  // tableau bytes of the LPs that do not fit in LDS
   if (K.share)
     for (int32_t i = 0; i < count; ++i)
-      if (wg_lds_bytes(m[i], n[i]) > limit) share_total += tableau_bytes(m[i], n[i]);
+      if (wg_lds_bytes(m[i], n[i]) > limit) share_total += stored_bytes(m[i], n[i], cd);
   // Wave-per-instance slices: the whole LDS split evenly (16-byte aligned).
   const int slots = std::max(0, std::min(K.wave_slots, kBT / kWave));
   const size_t slice = slots > 0 ? (limit / (size_t)slots) & ~size_t(15) : 0;
   std::vector<std::pair<double, int32_t>> wave;
   for (int32_t i = 0; i < count; ++i) {
-    const double bytes = tableau_bytes(m[i], n[i]);
+    const double bytes = stored_bytes(m[i], n[i], cd);
     work[(size_t)i] = bytes * (double)(m[i] + n[i]);  // proxy: tableau size x pivot-count scale
     const size_t lds_i = wg_lds_bytes(m[i], n[i]);
     if (slots > 0 && lds_i <= slice) {
@@ -166,7 +169,7 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
       P.klass[(size_t)i] = kClassLds;
       lds_wg = std::max(lds_wg, lds_i);
     } else {
-      max_vw = std::max<int64_t>(max_vw, (n[i] + m[i] + 1) / 2);
+      max_vw = std::max<int64_t>(max_vw, grid_layout(m[i], n[i], 1, cd).vw);
       if (K.team_min_bytes >= 0 && bytes >= (double)K.team_min_bytes) {
         int s = 0;
         if (K.team_size > 0) {
@@ -277,7 +280,7 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   for (int c = 0; c < P.n_classes; ++c) {
     uint64_t s = 0;
     if (!K.own_workspaces)
-      for (int32_t i : P.cls_list[c]) s = std::max<uint64_t>(s, grid_layout(m[i], n[i], 1).total);
+      for (int32_t i : P.cls_list[c]) s = std::max<uint64_t>(s, grid_layout(m[i], n[i], 1, cd).total);
     P.cls_ws_stride[c] = s;
     team_ws_total += (uint64_t)P.cls_teams[c] * s;
     nslots += (uint64_t)P.cls_teams[c] * 2 * P.cls_size[c];
@@ -285,7 +288,7 @@ BatchPlan plan_batch(int32_t count, const int64_t* m, const int64_t* n, const Ba
   if (!K.own_workspaces)
     for (int32_t i : P.single_list)
       if (P.klass[(size_t)i] == kClassSingle)
-        P.wg_ws_stride = std::max<uint64_t>(P.wg_ws_stride, grid_layout(m[i], n[i], 1).total);
+        P.wg_ws_stride = std::max<uint64_t>(P.wg_ws_stride, grid_layout(m[i], n[i], 1, cd).total);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
@@ -354,21 +357,23 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
       bw.counters, reinterpret_cast<BarrierSlot*>(base + P.off_slots), nslots);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+  const void* fn = P.condensed ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
   if (e != hipSuccess) return e;
   void* params[] = {&bw};
-  return hipLaunchCooperativeKernel((const void*)batch_kernel, dim3(P.nblocks), dim3(kBT), params,
+  return hipLaunchCooperativeKernel(fn, dim3(P.nblocks), dim3(kBT), params,
                                     (unsigned)P.lds_bytes, stream);
 }
 
-int batch_max_blocks(size_t lds_bytes) {
+int batch_max_blocks(size_t lds_bytes, bool condensed) {
+  const void* fn = condensed ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>;
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
       hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel, kBT, lds_bytes) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBT, lds_bytes) != hipSuccess) return 0;
   return per_cu * ncu;
 }
 

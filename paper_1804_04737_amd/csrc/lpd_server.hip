@@ -61,8 +61,8 @@ uint64_t input_bytes(int64_t m, int64_t n) { return (uint64_t)round_up(8 * (m * 
 
 // Device bytes a resident request holds: inputs, x and (for LPs that do not
 // fit in LDS) its grid-walk workspace.
-uint64_t footprint_of(int64_t m, int64_t n, bool lds) {
-  return input_bytes(m, n) + (lds ? 0 : grid_layout(m, n, 1).total);
+uint64_t footprint_of(int64_t m, int64_t n, bool lds, bool condensed) {
+  return input_bytes(m, n) + (lds ? 0 : grid_layout(m, n, 1, condensed).total);
 }
 
 // Smallest tableau share a workgroup gets under share sizing: below this the
@@ -241,7 +241,7 @@ void lpd_server::launch_epoch() {
   BatchPlan P = plan_batch(count, m.data(), n.data(), knobs, nblocks, lds_limit);
   hipError_t e = P.ok ? hipSuccess : hipErrorInvalidValue;
   if (e == hipSuccess) {
-    const int maxb = batch_max_blocks(P.lds_bytes);
+    const int maxb = batch_max_blocks(P.lds_bytes, P.condensed);
     if (maxb <= 0) e = hipErrorInvalidValue;
     else if (nblocks > maxb) P = plan_batch(count, m.data(), n.data(), knobs, maxb, lds_limit);
   }
@@ -271,7 +271,7 @@ void lpd_server::launch_epoch() {
     } else {
       // A pivot streams the tableau twice (read, write), split over the team.
       const double team = it.klass == kClassTeam ? (double)P.cls_size[it.tclass] : 1.0;
-      const double k = (double)opt.epoch_bytes_per_wg * team / (2.0 * tableau_bytes(r.m, r.n));
+      const double k = (double)opt.epoch_bytes_per_wg * team / (2.0 * stored_bytes(r.m, r.n, knobs.condensed));
       a.pivot_budget = (int64_t)std::max(1.0, std::min(k, 1e9));
     }
     it.ws = r.dws;
@@ -358,6 +358,7 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   s->knobs.team_min_bytes = s->opt.team_min_bytes != 0 ? s->opt.team_min_bytes : 2 * s->knobs.share_min_bytes_per_wg;
   s->knobs.own_workspaces = true;
   s->knobs.wave_slots = tuned_batch_knobs().wave_slots;
+  s->knobs.condensed = s->opt.full_tableau == 0;
   s->nslots = s->opt.max_resident;
   s->nblocks = p.multiProcessorCount;
   int lds = 0;
@@ -409,7 +410,7 @@ int64_t lpd_server_submit(lpd_server* s, int64_t m, int64_t n, const double* A, 
   if (m > (1 << 30) || n > (1 << 30) || m + n + 1 > (1 << 30)) return LPD_ERR_SIZE_OVERFLOW;
   // Same LDS test as the batch planner.
   const bool lds = wg_lds_bytes(m, n) + 256 <= s->lds_limit;
-  const uint64_t f = footprint_of(m, n, lds);
+  const uint64_t f = footprint_of(m, n, lds, s->knobs.condensed);
   if (f > s->budget) return LPD_ERR_TOO_LARGE;
   Request r;
   r.m = m;

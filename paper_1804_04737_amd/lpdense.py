@@ -47,13 +47,13 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
                 ("team_size", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("team_min_bytes", _I64), ("iterations", _P), ("team_bytes_per_wg", _I64),
-                ("wave_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wave_slots", ctypes.c_int32), ("full_tableau", ctypes.c_int32)]
 
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
                 ("pivots_per_epoch", _I64), ("max_resident", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("team_min_bytes", _I64), ("team_bytes_per_wg", _I64),
+                ("full_tableau", ctypes.c_int32), ("team_min_bytes", _I64), ("team_bytes_per_wg", _I64),
                 ("epoch_bytes_per_wg", _I64), ("admit_bytes_per_round", _I64)]
 
 
@@ -275,14 +275,15 @@ def pack_batch(lps, device="cuda") -> PackedBatch:
 
 def solve_batch(pb: PackedBatch, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
                 team_size: int = 0, team_min_bytes: int = 0, team_bytes_per_wg: int = 0,
-                wave_slots: int = 0, grid_blocks: int = 0, stream=None) -> PackedBatch:
+                wave_slots: int = 0, full_tableau: bool = False, grid_blocks: int = 0,
+                stream=None) -> PackedBatch:
     """lp_solve_batch on a PackedBatch (asynchronous; outputs land in pb)."""
     import numpy as np
     def hp(a):
         return a.ctypes.data_as(ctypes.c_void_p)
     opts = BatchOptions(float(eps_d), float(eps_p), int(max_iter), int(team_size), int(grid_blocks),
                         int(team_min_bytes), pb.iterations.data_ptr(), int(team_bytes_per_wg),
-                        int(wave_slots), 0)
+                        int(wave_slots), int(bool(full_tableau)))
     m = np.ascontiguousarray(pb.m, dtype=np.int64)
     n = np.ascontiguousarray(pb.n, dtype=np.int64)
     rc = load().lp_solve_batch(pb.count, hp(m), hp(n), pb.A.data_ptr(), hp(pb.A_off), pb.b.data_ptr(),
@@ -323,9 +324,10 @@ class Server:
     def __init__(self, budget_bytes: int, *, device: int = 0, pivots_per_epoch: int = 0,
                  max_resident: int = 0, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = 0,
                  team_min_bytes: int = 0, team_bytes_per_wg: int = 0, epoch_bytes_per_wg: int = 0,
-                 admit_bytes_per_round: int = 0):
+                 admit_bytes_per_round: int = 0, full_tableau: bool = False):
         opts = ServerOptions(float(eps_d), float(eps_p), int(max_iter), int(pivots_per_epoch),
-                             int(max_resident), 0, int(team_min_bytes), int(team_bytes_per_wg),
+                             int(max_resident), int(bool(full_tableau)), int(team_min_bytes),
+                             int(team_bytes_per_wg),
                              int(epoch_bytes_per_wg), int(admit_bytes_per_round))
         self._lib = load()
         h = self._lib.lpd_server_create(int(device), int(budget_bytes), ctypes.byref(opts))

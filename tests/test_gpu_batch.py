@@ -31,11 +31,12 @@ def _mixed_lps(seed, count=40):
     return [lpgen.dense_lp(m, n, 1000 * seed + i) for i, (m, n) in enumerate(shapes)]
 
 
+@pytest.mark.parametrize("full", [False, True], ids=["condensed", "full"])
 @pytest.mark.parametrize("team_size,team_min", [(0, 0), (1, 0), (2, 200_000), (8, 200_000), (32, 1_000_000)])
-def test_batch_equals_oracle(team_size, team_min):
+def test_batch_equals_oracle(team_size, team_min, full):
     lps = _mixed_lps(1)
-    announce(f"batch of {len(lps)} team_size={team_size} team_min={team_min}")
-    xs, obj, st, it = _run_batch(lps, team_size=team_size, team_min_bytes=team_min)
+    announce(f"batch of {len(lps)} team_size={team_size} team_min={team_min} full_tableau={full}")
+    xs, obj, st, it = _run_batch(lps, team_size=team_size, team_min_bytes=team_min, full_tableau=full)
     for i, (A, b, c) in enumerate(lps):
         ref = oracle.solve(A, b, c)
         assert st[i] == ref.status and it[i] == ref.iterations, i
@@ -49,7 +50,8 @@ def test_batch_order_and_single_solve_agree():
     announce("batch order invariance")
     xs1, obj1, st1, it1 = _run_batch(lps, team_size=4, team_min_bytes=300_000)
     perm = np.random.default_rng(5).permutation(len(lps))
-    xs2, obj2, st2, it2 = _run_batch([lps[p] for p in perm], team_size=16, team_min_bytes=100_000)
+    xs2, obj2, st2, it2 = _run_batch([lps[p] for p in perm], team_size=16, team_min_bytes=100_000,
+                                     full_tableau=True)
     dev = torch.device("cuda")
     for j, p in enumerate(perm):
         assert np.array_equal(bits(xs1[p]), bits(xs2[j])) and bits([obj1[p]])[0] == bits([obj2[j]])[0]

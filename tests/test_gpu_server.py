@@ -45,15 +45,15 @@ def _mix(seed, count):
     return [lpgen.dense_lp(m, n, 7000 + 100 * seed + i) for i, (m, n) in enumerate(shapes)]
 
 
-@pytest.mark.parametrize("ppe", [1, 7, 0])
-def test_server_results_equal_oracle(ppe):
+@pytest.mark.parametrize("ppe,full", [(1, False), (7, False), (0, False), (3, True)])
+def test_server_results_equal_oracle(ppe, full):
     """Teams of several sizes (low thresholds) and a small pivot budget per
     epoch: each LP is suspended and resumed many times, by teams whose size
-    changes with the resident mix."""
+    changes with the resident mix; condensed and full tableaux."""
     lps = _mix(1, 24)
-    announce(f"server mix of {len(lps)} pivots_per_epoch={ppe}")
+    announce(f"server mix of {len(lps)} pivots_per_epoch={ppe} full_tableau={full}")
     with lpdense.Server(8 << 30, pivots_per_epoch=ppe, team_min_bytes=150_000,
-                        team_bytes_per_wg=60_000) as srv:
+                        team_bytes_per_wg=60_000, full_tableau=full) as srv:
         ids = [srv.submit(*lp) for lp in lps]
         got = _drain(srv, len(ids))
         st = srv.stats()
@@ -124,7 +124,7 @@ def test_server_rejects_and_edge_cases():
     ]
     with lpdense.Server(1 << 20) as tiny:
         with pytest.raises(lpdense.LpdError) as e:
-            tiny.submit(*lpgen.dense_lp(200, 300, 1))   # footprint above the whole budget
+            tiny.submit(*lpgen.dense_lp(400, 500, 1))   # footprint above the whole budget
         assert e.value.code == -7
     with lpdense.Server(1 << 30, pivots_per_epoch=4, max_iter=7) as srv:
         ids = [srv.submit(*lp) for lp in lps]
