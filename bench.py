@@ -263,6 +263,60 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def shapes_bench(args):
+    """The paper's shape grid: m, n in {256, ..., 8192} (36 shapes), one full
+    solve each on the full and on the condensed tableau, with the chosen
+    generator (seed fixed).  Reports pivots, ms and pivots/s per shape; the
+    paper's observation that more variables than constraints solve faster is
+    about wall time, which this splits into pivot count and time per pivot."""
+    import torch
+
+    from paper_1804_04737_amd import lpdense, lpgen
+    lpdense.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    gen = lpgen.paper_lp if args.generator == "paper" else lpgen.dense_lp
+    rows = []
+    t_all = 0.0
+    piv_all = 0
+    for m in lpgen.PAPER_SIZES:
+        for n in lpgen.PAPER_SIZES:
+            A, b, c = gen(m, n, args.seed)
+            tA, tb, tc = (torch.from_numpy(v).to(dev) for v in (A, b, c))
+            row = {"m": m, "n": n}
+            for name, sched in (("full", lpdense.SCHED_AUTO), ("condensed", lpdense.SCHED_GRID_CONDENSED)):
+                lpdense.solve_dense_ex(tA, tb, tc, want_y=False, schedule=sched, stream=stream, max_iter=2)
+                s0 = torch.cuda.Event(enable_timing=True)
+                s1 = torch.cuda.Event(enable_timing=True)
+                s0.record(stream)
+                r = lpdense.solve_dense_ex(tA, tb, tc, want_y=False, schedule=sched, stream=stream,
+                                           max_iter=2 * (m + n))
+                s1.record(stream)
+                torch.cuda.synchronize()
+                ms = s0.elapsed_time(s1)
+                piv = int(r.iterations.item())
+                row[f"{name}_ms"] = round(ms, 3)
+                row[f"{name}_pivots_per_s"] = round(piv / (ms / 1e3), 1) if ms > 0 else None
+                row["pivots"] = piv
+                row["status"] = lpdense.STATUS_NAMES[int(r.status.item())]
+                if name == "condensed":
+                    t_all += ms / 1e3
+                    piv_all += piv
+            rows.append(row)
+            log(json.dumps(row))
+            del tA, tb, tc
+    out = {
+        "metric": METRIC, "value": round(piv_all / t_all, 1), "unit": "pivots/s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"shape grid m, n in {list(lpgen.PAPER_SIZES)}, {args.generator} generator, "
+                               f"seed {args.seed}, one solve per shape and tableau form (at most 2 (m+n) "
+                               f"pivots); value = all "
+                               f"condensed pivots / all condensed time", "shapes": rows},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,7 +333,9 @@ def main():
                     help="after the timed steps, run one more solve with per-phase device timestamps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
-    ap.add_argument("--workload", choices=["dense", "batch", "serve"], default="dense")
+    ap.add_argument("--workload", choices=["dense", "batch", "serve", "shapes"], default="dense")
+    ap.add_argument("--generator", choices=["dense", "paper"], default="dense",
+                    help="dense / shapes: the main generator, or the paper-style one (zeros in A, b = A x0)")
     ap.add_argument("--schedule", choices=["auto", "condensed"], default="auto",
                     help="dense: full tableau (auto: grid for large LPs) or the condensed tableau "
                          "(nonbasic columns only, bitwise-identical results)")
@@ -315,6 +371,8 @@ def main():
         return batch_bench(args)
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "shapes":
+        return shapes_bench(args)
 
     import numpy as np
     import torch
@@ -324,8 +382,8 @@ def main():
     lpdense.load()
     dev = torch.device("cuda:0")
     m, n = args.m, args.n
-    log(f"generating {m}x{n} LP seed {args.seed}")
-    A, b, c = lpgen.dense_lp(m, n, args.seed)
+    log(f"generating {m}x{n} LP seed {args.seed} ({args.generator} generator)")
+    A, b, c = (lpgen.paper_lp if args.generator == "paper" else lpgen.dense_lp)(m, n, args.seed)
     tA = torch.from_numpy(A).to(dev)
     tb = torch.from_numpy(b).to(dev)
     tc = torch.from_numpy(c).to(dev)
@@ -379,7 +437,7 @@ def main():
     avg_ms = sum(ev_ms) / len(ev_ms)
     achieved = bytes_per_pivot * (total_piv / args.steps) / (avg_ms / 1e3) / 1e9
     traffic = (counter_traffic(pivots[0]) if (m, n, args.seed) == (8192, 8192, 0) and args.schedule == "auto"
-               else None)
+               and args.generator == "dense" else None)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 1)}
@@ -419,7 +477,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"dense LP max c^T x, Ax<=b, x>=0, m={m}, n={n}, seed {args.seed}, "
-                               f"full solve from the slack basis (Dantzig, lowest-index ties)"
+                               + ("paper-style generator, " if args.generator == "paper" else "")
+                               + "full solve from the slack basis (Dantzig, lowest-index ties)"
                                + ("; condensed tableau (nonbasic columns only)" if args.schedule == "condensed"
                                   else ""),
                    "schedule": args.schedule,

@@ -63,3 +63,38 @@ def poisson_arrivals(rate: float, count: int, seed: int = 0):
     """Arrival times (s) of a Poisson process: cumulative exponential gaps."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+# The paper's experiments (Section 4) use problem shapes m, n in this set.
+PAPER_SIZES = (256, 512, 1024, 2048, 4096, 8192)
+
+
+def paper_lp(m: int, n: int, seed: int, density: float = 0.9):
+    """A second workload with the behaviour of the paper's random generator
+    (Section 4): a dense-ish A with about `density` of its entries nonzero,
+    values between 0 and 50, and b built from a random non-negative point so
+    that every instance is feasible.  Written from that description (the
+    printed listing is garbled and is not reproduced); integer values keep
+    every draw, b and c exact on any machine:
+
+        rng  = numpy.random.default_rng(seed)
+        mask = rng.random((m, n)) < density
+        A    = mask * rng.integers(1, 51, (m, n))       (float64)
+        x0   = rng.integers(0, 11, n)                    (a point with A x0 = b)
+        b    = A @ x0                                    (exact: integers < 2^53)
+        repeat: u = rng.integers(-1, 2, m); c = A^T u    until some c_j > 0
+
+    A >= 0 with no empty column (almost surely) keeps max c^T x bounded; x0
+    and x = 0 are feasible.  c has both signs, so pricing meets many ties and
+    zero reduced costs, unlike dense_lp.
+    """
+    rng = np.random.default_rng(seed)
+    mask = rng.random((m, n)) < density
+    A = (mask * rng.integers(1, 51, (m, n))).astype(np.float64)
+    x0 = rng.integers(0, 11, n).astype(np.float64)
+    b = A @ x0
+    while True:
+        u = rng.integers(-1, 2, m).astype(np.float64)
+        c = A.T @ u
+        if np.any(c > 0):
+            return A, b, c

@@ -142,3 +142,17 @@ def test_medium_full_solve(m, n, seed, schedule):
     assert_bitwise_equal(g, ref)
     rp, rd, gap = lp_checks.residuals(A, b, c, g.x, g.y)
     assert rp <= 1e-9 and rd <= 1e-9 and gap <= 1e-9
+
+
+@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, GRID, CD], ids=["auto", "grid", "condensed"])
+@pytest.mark.parametrize("m,n,seed", [(30, 40, 1), (256, 512, 2), (512, 256, 3), (700, 900, 4)])
+def test_paper_generator_instances(m, n, seed, schedule):
+    """The second workload (zeros in A, b = A x0, c of both signs: many
+    pricing ties and degenerate pivots) gives the oracle's bits too."""
+    A, b, c = lpgen.paper_lp(m, n, seed)
+    announce(f"paper-style {m}x{n} seed={seed} schedule={schedule}")
+    small = m * n <= 300_000
+    g = gpu_solve(A, b, c, schedule=schedule, want_tableau=small)
+    ref = oracle.solve(A, b, c, want_tableau=small)
+    assert ref.status == oracle.OPTIMAL
+    assert_bitwise_equal(g, ref, check_tableau=small)
