@@ -61,9 +61,11 @@ typedef enum lpd_status {
     LPD_ITERATION_LIMIT = 2,  /* max_iter pivots done, not yet optimal */
     LPD_INFEASIBLE_START = 3, /* some b_i < 0: slack basis infeasible */
     LPD_NUMERICAL = 4,        /* NaN/Inf in the input or met while pivoting */
-    LPD_DEVICE_TIMEOUT = 5    /* a grid-wide barrier of the persistent kernel did not
+    LPD_DEVICE_TIMEOUT = 5,   /* a grid-wide barrier of the persistent kernel did not
                                  complete within its watchdog time (about 10 s); the
                                  outputs are undefined.  Not expected in normal use. */
+    LPD_INFEASIBLE = 6        /* lp_solve_general only: phase I ends with artificial
+                                 variables left positive, no feasible point */
 } lpd_status;
 
 /* Synchronous argument / launch errors (negative return values). */
@@ -305,6 +307,50 @@ int lpd_server_get_stats(lpd_server *server, lpd_server_stats *out);
 /* Finishes every submitted request (their completions are then dropped),
  * stops the worker and frees the server. */
 void lpd_server_destroy(lpd_server *server);
+
+/*
+ * General LPs (two-phase method).  Section 2 states the problem with rows
+ * A x = b and treats the canonical <= form with b >= 0, where the slack basis
+ * is a feasible start.  lp_solve_general accepts rows of any sense and
+ * right-hand sides of any sign:
+ *
+ *     maximize c^T x  subject to  A_i x (<=, =, >=) b_i,  x >= 0.
+ *
+ * Phase I: every row is scaled by +1 or -1 so that its right-hand side is
+ * >= 0; a row that then reads ">=" gets a surplus column, and every row
+ * whose slack cannot start basic (">=" or "=") gets an artificial variable
+ * as its basic variable.  That is an LP of the canonical form above with n +
+ * (number of surplus columns) structural variables, whose objective is the
+ * sum of the artificial rows; it is solved by the pivot kernels of
+ * lp_solve_dense_ex.  The LP is feasible iff that optimum reaches the sum of
+ * the artificial rows' right-hand sides (relative tolerance 1e-9); else the
+ * status is LPD_INFEASIBLE.
+ * Phase II restarts from phase I's final basis: the nonbasic non-artificial
+ * columns of phase I's final tableau become the structural columns of a
+ * second canonical LP, whose slack basis is phase I's basis, with the
+ * original costs reduced by that basis (c_N - A_N^T c_B, one sequential sum
+ * per column); an artificial variable that stays basic at level zero gets a
+ * mirrored row so that it stays zero.  The second solve gives the optimum;
+ * x of the original variables is read back, and obj = c^T x.
+ *
+ *   m, n        sizes (host)
+ *   A, b, c     device arrays, as lp_solve_dense (b of any sign)
+ *   sense       host array of m lpd_row_sense values, or NULL for all <=
+ *   opt         may be NULL; schedule, eps and max_iter apply to each phase
+ *   x, obj, status  device outputs (x: n entries)
+ *   iterations  optional device output: pivots of both phases
+ * Unlike the other solve calls this one synchronises `stream`: the phase II
+ * layout depends on phase I's basis.  Returns LPD_SUCCESS or an lpd_error.
+ */
+typedef enum lpd_row_sense {
+    LPD_ROW_LE = 0,
+    LPD_ROW_EQ = 1,
+    LPD_ROW_GE = 2
+} lpd_row_sense;
+
+int lp_solve_general(int64_t m, int64_t n, const double *A, const double *b, const double *c,
+                     const int8_t *sense, const lpd_options *opt, double *x, double *obj,
+                     int32_t *status, int64_t *iterations, hipStream_t stream);
 
 /* Device workspace (bytes) a single solve of an m x n LP allocates. */
 uint64_t lpd_workspace_bytes(int64_t m, int64_t n);

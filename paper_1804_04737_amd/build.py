@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblpdense.so")
-SOURCES = ["lpd_api.hip", "lpd_grid.hip", "lpd_wg.hip", "lpd_batch.hip", "lpd_server.hip"]
+SOURCES = ["lpd_api.hip", "lpd_grid.hip", "lpd_wg.hip", "lpd_batch.hip", "lpd_server.hip", "lpd_general.hip"]
 
 # -ffp-contract=off: the kernels spell out every fused multiply-add they want.
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.

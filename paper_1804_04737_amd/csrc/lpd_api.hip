@@ -359,6 +359,7 @@ const char* lpd_status_string(int32_t s) {
     case LPD_INFEASIBLE_START: return "INFEASIBLE_START";
     case LPD_NUMERICAL: return "NUMERICAL";
     case LPD_DEVICE_TIMEOUT: return "DEVICE_TIMEOUT";
+    case LPD_INFEASIBLE: return "INFEASIBLE";
     default: return "unknown";
   }
 }

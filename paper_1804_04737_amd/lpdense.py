@@ -14,13 +14,14 @@ from dataclasses import dataclass
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblpdense.so")
 
-OPTIMAL, UNBOUNDED, ITERATION_LIMIT, INFEASIBLE_START, NUMERICAL, DEVICE_TIMEOUT = range(6)
+OPTIMAL, UNBOUNDED, ITERATION_LIMIT, INFEASIBLE_START, NUMERICAL, DEVICE_TIMEOUT, INFEASIBLE = range(7)
 STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "NUMERICAL",
-                "DEVICE_TIMEOUT")
+                "DEVICE_TIMEOUT", "INFEASIBLE")
+ROW_LE, ROW_EQ, ROW_GE = 0, 1, 2
 SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED = 0, 1, 2, 3
 
 # Exported symbols, as declared in include/lpdense.h.
-EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lpd_server_create",
+EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lp_solve_general", "lpd_server_create",
            "lpd_server_submit", "lpd_server_poll", "lpd_server_get_stats", "lpd_server_destroy",
            "lpd_workspace_bytes", "lpd_error_string", "lpd_status_string", "lpd_version")
 
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.lp_solve_batch.restype = ctypes.c_int
     lib.lp_solve_batch.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                    ctypes.POINTER(BatchOptions), _P]
+    lib.lp_solve_general.restype = ctypes.c_int
+    lib.lp_solve_general.argtypes = [_I64, _I64, _P, _P, _P, _P, ctypes.POINTER(Options), _P, _P, _P, _P, _P]
     lib.lpd_server_create.restype = _P
     lib.lpd_server_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ServerOptions)]
     lib.lpd_server_submit.restype = _I64
@@ -397,3 +400,42 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class GeneralResult:
+    x: "object"
+    obj: "object"
+    status: "object"
+    iterations: "object"
+
+
+def solve_general(A, b, c, sense=None, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
+                  schedule: int = SCHED_AUTO, grid_blocks: int = 0, stream=None) -> GeneralResult:
+    """lp_solve_general on device tensors (two-phase method; rows <=, =, >=
+    given by `sense`, a sequence of ROW_LE / ROW_EQ / ROW_GE, default all <=).
+    Synchronous: returns device tensors that are ready."""
+    import numpy as np
+    import torch
+    m, n = A.shape
+    _check_dev("A", A, torch.float64, m * n)
+    _check_dev("b", b, torch.float64, m)
+    _check_dev("c", c, torch.float64, n)
+    dev = A.device
+    res = GeneralResult(torch.empty(n, dtype=torch.float64, device=dev),
+                        torch.empty(1, dtype=torch.float64, device=dev),
+                        torch.empty(1, dtype=torch.int32, device=dev),
+                        torch.empty(1, dtype=torch.int64, device=dev))
+    sn = None
+    if sense is not None:
+        sn = np.ascontiguousarray(np.asarray(sense, dtype=np.int8))
+        if sn.shape != (m,):
+            raise ValueError("sense must have one entry per row")
+    opts = Options(float(eps_d), float(eps_p), int(max_iter), int(schedule), int(grid_blocks))
+    rc = load().lp_solve_general(m, n, A.data_ptr(), b.data_ptr(), c.data_ptr(),
+                                 None if sn is None else sn.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(opts), res.x.data_ptr(), res.obj.data_ptr(),
+                                 res.status.data_ptr(), res.iterations.data_ptr(), _stream_handle(stream))
+    if rc != 0:
+        raise LpdError(rc, "lp_solve_general")
+    return res

@@ -98,3 +98,34 @@ def paper_lp(m: int, n: int, seed: int, density: float = 0.9):
         c = A.T @ u
         if np.any(c > 0):
             return A, b, c
+
+
+def general_lp(m: int, n: int, seed: int, p_eq: float = 0.2, p_ge: float = 0.3, bounded: bool = True):
+    """A general LP for the two-phase path: rows of every sense and
+    right-hand sides of both signs, feasible by construction at a point x0.
+
+        rng   = numpy.random.default_rng(seed)
+        A     = rng.integers(-10, 11, (m, n))      (float64)
+        x0    = rng.integers(0, 6, n)
+        slack = rng.integers(0, 6, m)
+        sense = LE / EQ / GE with probabilities 1-p_eq-p_ge, p_eq, p_ge
+        b     = A x0 + slack (LE), A x0 (EQ), A x0 - slack (GE)
+        c     = rng.integers(-5, 11, n)
+    With bounded=True the last row is replaced by sum(x) <= sum(x0) + 10 (LE),
+    which keeps the optimum finite.  Returns (A, b, c, sense) with sense as
+    int8 codes 0 (<=), 1 (=), 2 (>=).
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-10, 11, (m, n)).astype(np.float64)
+    x0 = rng.integers(0, 6, n).astype(np.float64)
+    slack = rng.integers(0, 6, m).astype(np.float64)
+    u = rng.random(m)
+    sense = np.where(u < p_eq, 1, np.where(u < p_eq + p_ge, 2, 0)).astype(np.int8)
+    ax = A @ x0
+    b = np.where(sense == 0, ax + slack, np.where(sense == 2, ax - slack, ax))
+    c = rng.integers(-5, 11, n).astype(np.float64)
+    if bounded:
+        A[-1] = 1.0
+        b[-1] = x0.sum() + 10.0
+        sense[-1] = 0
+    return A, b, c, sense
