@@ -329,6 +329,8 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-condensed", action="store_true",
+                    help="dense: skip the extra timing of the same LP on the condensed tableau")
     ap.add_argument("--phases", action="store_true",
                     help="after the timed steps, run one more solve with per-phase device timestamps")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -364,7 +366,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
-              f"(one LP per GPU; see the sharding design in DESIGN.md).", file=sys.stderr)
+              f"(one LP per GPU; sharding over several GPUs is not built).", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
@@ -458,6 +460,31 @@ def main():
                       "release": round(d[3], 2), "detect": round(d[4], 2), "reduce": round(d[5], 2)}
             log(f"phases (median us/pivot): {phases}")
 
+    # Same LP on the condensed tableau (bitwise-identical results, fewer bytes
+    # per pivot): reported beside the full-tableau figures.
+    condensed = None
+    if args.schedule == "auto" and not args.no_condensed:
+        cd = lpdense.SCHED_GRID_CONDENSED
+        lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=cd, want_y=False, stream=stream)
+        cs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ce = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        rs = []
+        for k in range(args.steps):
+            cs[k].record(stream)
+            rs.append(lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=cd, want_y=False,
+                                             stream=stream))
+            ce[k].record(stream)
+        torch.cuda.synchronize()
+        cms = sum(a.elapsed_time(b) for a, b in zip(cs, ce)) / args.steps
+        cpiv = int(rs[0].iterations.item())
+        same = all(bool(torch.equal(r.x.view(torch.int64), results[0].x.view(torch.int64))) for r in rs)
+        cbytes = 16.0 * (m + 1) * (n + 1)
+        condensed = {"pivots_per_s": round(cpiv / (cms / 1e3), 2), "ms_per_solve": round(cms, 3),
+                     "pivots_per_step": cpiv, "bytes_per_pivot": int(cbytes),
+                     "stored_bytes_GBps": round(cbytes * cpiv / (cms / 1e3) / 1e9, 1),
+                     "x_bitwise_equal_to_full_tableau": same}
+        log(f"condensed tableau: {condensed}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -485,7 +512,7 @@ def main():
                    "m": m, "n": n, "pivots_per_step": pivots[0],
                    "status": lpdense.STATUS_NAMES[statuses[0]],
                    "bytes_per_pivot": int(bytes_per_pivot),
-                   "max_iter": args.max_iter, "phases_us": phases},
+                   "max_iter": args.max_iter, "phases_us": phases, "condensed_tableau": condensed},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
