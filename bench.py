@@ -365,7 +365,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
+        print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark runs on one GPU only "
               f"(one LP per GPU; sharding over several GPUs is not built).", file=sys.stderr)
         sys.exit(2)
 
