@@ -42,7 +42,7 @@ int device_info(DeviceInfo* out) {
     if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return;
     if (!p.cooperativeLaunch) return;
     // Keep freed workspace in the stream-ordered pool instead of returning it
-    // to the driver after every solve.
+    // to the device driver after every solve.
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
       uint64_t threshold = UINT64_MAX;
