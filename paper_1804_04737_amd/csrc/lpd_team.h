@@ -50,8 +50,9 @@ constexpr int kTicks = 8;         // phase_ticks entries per pivot
 constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column elements per workgroup)
 constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
-constexpr int kChunkSteps = 8;                 // dynamic sweep chunk: 8 x NT vectors
-constexpr int64_t kDynMinSteps = 192;          // sweeps shorter than this are all static
+constexpr int kChunkSteps = 3;                 // dynamic sweep chunk: 3 x NT vectors
+constexpr int64_t kStaticSteps = 16;           // static grid steps before the dynamic part
+constexpr int64_t kDynMinSteps = 96;           // sweeps shorter than this are all static
 
 // Tableau workspaces are always device global memory.  Saying so lets the
 // compiler use global (not flat) loads and stores even where the pointer was
@@ -218,17 +219,20 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const int32_t pub_v0 = (int32_t)((int64_t)vw * tm.rank / nb);
   const int32_t pub_v1 = (int32_t)((int64_t)vw * (tm.rank + 1) / nb);
   uint32_t& epoch = *tm.epoch;
-  // Guided split of each sweep: the first elements (flat index below
-  // e_static) follow the static grid-stride walk; the last ~1/8, in chunks
-  // of kChunkSteps x NT vectors, go to whichever workgroup of the team asks
-  // next (atomic ticket counter), so that workgroups that ran slower this
-  // pivot leave their share of the tail to faster ones.
+  // Dynamic split of each sweep: the first kStaticSteps grid steps (flat
+  // index below e_static) follow the static grid-stride walk, which covers
+  // the latency of the first tickets; the rest, in chunks of kChunkSteps x
+  // NT vectors, go to whichever workgroup of the team asks next (atomic
+  // ticket counter), so that workgroups that run slower leave work to faster
+  // ones up to the end of the sweep.  Measured at 8192 x 8192 on 256
+  // workgroups, 3-step chunks beat 2 (the one counter's atomics become the
+  // limit) and 4..8 (coarser balance).
   const int64_t e_total = (int64_t)m * vw;
   const int64_t steps_total = (e_total + G - 1) / G;
   // The dynamic part costs a few microseconds per pivot (ticket broadcasts,
   // the last chunk's latency); it only pays off on long sweeps.
   const bool dyn = nb > 1 && steps_total >= kDynMinSteps;
-  const int64_t e_static = dyn ? (steps_total - steps_total / 8) * G : e_total;
+  const int64_t e_static = dyn ? min((int64_t)kStaticSteps * G, e_total) : e_total;
   const int64_t chunk = (int64_t)kChunkSteps * NT;
   const uint32_t n_chunks = dyn ? (uint32_t)((e_total - e_static + chunk - 1) / chunk) : 0u;
   const int64_t n_static = e_static > gid ? (e_static - gid - 1) / G + 1 : 0;
@@ -504,11 +508,18 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         }
         if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
       };
-      // The first ticket is requested before the static walk, which hides
-      // the atomic's latency (this pivot's counter was reset a pivot ago).
+      // Two tickets are kept in flight per workgroup: both are requested
+      // before the static walk, and each is requested again as soon as the
+      // chunk it named has started, so an atomic's latency hides behind two
+      // chunks.  (This pivot's counter was reset a pivot ago.)  Requests of
+      // one thread to one counter are ordered, so tickets arrive increasing
+      // in the order they are used.
       uint32_t* ctr = w.tickets + 32 * (iter & 1);
-      uint32_t nxt = 0;
-      if (dyn && tid == 0) nxt = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t tk_a = 0, tk_b = 0;
+      if (dyn && tid == 0) {
+        tk_a = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tk_b = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       int32_t i = i_start, v = v_start;
       const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
       const int64_t row_step = (int64_t)step_q * ldv;
@@ -561,21 +572,22 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         }
       }
       if (dyn) {
-        // Dynamic tail of the sweep.  Ticket c covers flat elements
+        // Dynamic part of the sweep.  Ticket c covers flat elements
         // e_static + c * chunk + [0, chunk); thread tid takes every NT-th.
-        // Lane 0 asks for the next ticket after its first element of the
-        // current chunk, so the atomic's latency hides behind that chunk.
-        for (int par = 0;; par ^= 1) {
-          if (tid == 0) s_tk[par] = nxt;
+        // `tkt` is the ticket register of this chunk; `par` selects the LDS
+        // slot that broadcasts it (two slots: the next chunk's write cannot
+        // overtake a slow reader of this one).
+        auto run_chunk = [&](uint32_t& tkt, int par) -> bool {
+          if (tid == 0) s_tk[par] = tkt;
           __syncthreads();
           const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_tk[par]);
-          if (c >= n_chunks) break;
+          if (c >= n_chunks) return false;
           const int64_t e0 = e_static + (int64_t)c * chunk + tid;
           int32_t ii = (int32_t)(e0 / vw), vv = (int32_t)(e0 % vw);
           for (int qq = 0; qq < kChunkSteps; ++qq) {
             if (ii < m) element(ii, vv);
             if (qq == 0 && tid == 0)
-              nxt = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              tkt = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             vv += dq_r;
             ii += dq_q;
             if (vv >= vw) {
@@ -583,6 +595,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
               ++ii;
             }
           }
+          return true;
+        };
+        while (run_chunk(tk_a, 0) && run_chunk(tk_b, 1)) {
         }
       }
       __syncthreads();

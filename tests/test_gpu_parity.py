@@ -156,3 +156,21 @@ def test_paper_generator_instances(m, n, seed, schedule):
     ref = oracle.solve(A, b, c, want_tableau=small)
     assert ref.status == oracle.OPTIMAL
     assert_bitwise_equal(g, ref, check_tableau=small)
+
+
+@pytest.mark.parametrize("blocks,schedule", [(2, GRID), (3, GRID), (5, GRID), (2, CD), (3, CD)],
+                         ids=["grid2", "grid3", "grid5", "condensed2", "condensed3"])
+def test_dynamic_sweep_bitwise(blocks, schedule):
+    """A sweep of at least 96 grid steps hands its tail out in chunks through
+    a ticket counter.  On a grid of a few workgroups a 700 x 1000 LP is long
+    enough for that; a chunk lost, done twice or taken from the wrong pivot's
+    counter would change bits, so the whole tableau must match the oracle."""
+    m, n = 700, 1000
+    vw = (n + 1) // 2 if schedule == CD else (n + m + 1) // 2
+    assert -(-m * vw // (blocks * 1024)) >= 96  # long enough for the ticket path
+    A, b, c = lpgen.dense_lp(m, n, 11)
+    announce(f"dynamic sweep {m}x{n} blocks={blocks} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, grid_blocks=blocks, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert ref.status == oracle.OPTIMAL
+    assert_bitwise_equal(g, ref, check_tableau=True)
