@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
       GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, 1, CD), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
-      team_solve<kBT, 0, CD>(it.a, w, solo, smem);
+      team_solve<kBT, 0, CD, false>(it.a, w, solo, smem);
     }
   }
 

@@ -57,6 +57,12 @@ struct alignas(128) BarrierSlot {
 };
 static_assert(sizeof(BarrierSlot) == 128, "slot must fill one 128 B line");
 
+// Chunk-ticket counters of the update sweep's dynamic part: kTicketCounters
+// counters, each in its own block of kTicketStride uint32 (4 KiB), each with
+// one word per pivot parity (128 B apart).
+constexpr int kTicketCounters = 2;
+constexpr int kTicketStride = 1024;
+
 // Device workspace of the persistent grid solve (all pointers into one allocation).
 struct GridWork {
   int64_t ld;      // row stride of T in doubles (multiple of 32)
@@ -71,7 +77,7 @@ struct GridWork {
   // Condensed tableau only (T holds the n nonbasic columns):
   int32_t* lab;    // n: variable held by each stored column
   int32_t* col_of; // n+m: stored column of each nonbasic variable, -1 if basic
-  uint32_t* tickets;   // chunk tickets of the sweep's dynamic part: [0] and [32], by pivot parity
+  uint32_t* tickets;   // sweep chunk tickets: counter h of pivot parity q at [h * kTicketStride + 32 q]
   BarrierSlot* slots; // 2 * nblocks
   int32_t cap_cap;     // capacity of the LDS capture list (entries)
   int32_t lds_vecs;    // capacity of the LDS pivot-row buffer (16-byte vectors, >= vw)
@@ -108,7 +114,7 @@ __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblo
   L.off_pos = take((uint64_t)(n + m) * 4);
   L.off_lab = take(condensed ? (uint64_t)(n + 1) * 4 : 0);  // n + 1: read in pairs
   L.off_colof = take(condensed ? (uint64_t)(n + m) * 4 : 0);
-  L.off_tickets = take(256);  // two counters on separate 128 B lines
+  L.off_tickets = take((uint64_t)kTicketCounters * kTicketStride * 4);  // one 4 KiB block per counter
   L.off_slots = take(2ull * nblocks * sizeof(BarrierSlot));
   L.total = off;
   return L;

@@ -50,9 +50,9 @@ constexpr int kTicks = 8;         // phase_ticks entries per pivot
 constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column elements per workgroup)
 constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
-constexpr int kChunkSteps = 3;                 // dynamic sweep chunk: 3 x NT vectors
+constexpr int kChunkSteps = 2;                 // dynamic sweep chunk: 2 x NT vectors
 constexpr int64_t kStaticSteps = 16;           // static grid steps before the dynamic part
-constexpr int64_t kDynMinSteps = 96;           // sweeps shorter than this are all static
+constexpr int64_t kDynMinSteps = 48;           // sweeps shorter than this are all static
 
 // Tableau workspaces are always device global memory.  Saying so lets the
 // compiler use global (not flat) loads and stores even where the pointer was
@@ -68,6 +68,23 @@ __device__ __forceinline__ double gld(const double* p) { return *(const gdouble*
 __device__ __forceinline__ void gst(double* p, double v) { *(gdouble*)p = v; }
 __device__ __forceinline__ dbl2 gld2(const dbl2* p) { return *(const gdbl2*)p; }
 __device__ __forceinline__ void gst2(dbl2* p, dbl2 v) { *(gdbl2*)p = v; }
+
+// Gives a wave-uniform value a scalar register of its own.  Fields of the
+// kernel's argument block are otherwise loaded as wide register tuples, and
+// the register allocator spills and reloads such a tuple as a whole, also
+// inside the sweep where one field of it is needed.  (Where the value was
+// loaded into vector registers, e.g. from a batch descriptor, the first
+// lane's copy is taken: the callers pass values that every lane agrees on.)
+template <class T>
+__device__ __forceinline__ T own_sreg(T v) {
+  static_assert(sizeof(T) % 4 == 0, "32-bit words only");
+  uint32_t wd[sizeof(T) / 4];
+  __builtin_memcpy(wd, &v, sizeof(T));
+  for (unsigned q = 0; q < sizeof(T) / 4; ++q) wd[q] = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)wd[q]);
+  __builtin_memcpy(&v, wd, sizeof(T));
+  asm("" : "+s"(v));
+  return v;
+}
 
 // Grid-wide lexicographic arg-min that doubles as the barrier.
 // `c` is this workgroup's reduced candidate (identical in all its threads).
@@ -190,7 +207,9 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 // and RN(1/p) in row l, so every value equals the full tableau's bit for bit.
 // basis[l] changes one pivot late (all workgroups read basis[] while the
 // leader would otherwise write it): the row of the previous pivot holds kprev.
-template <int NT, int MAP, bool CD = false>
+// DYN = false compiles the dynamic sweep out (for callers whose teams are
+// always one workgroup, which never use it).
+template <int NT, int MAP, bool CD = false, bool DYN = true>
 __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm, unsigned char* smem) {
   Cand* scratch = reinterpret_cast<Cand*>(smem);
   dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
@@ -205,10 +224,12 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
 
   const int nb = tm.size, tid = threadIdx.x;
   const bool leader = tm.rank == 0;
-  const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m;
+  const int32_t m = own_sreg((int32_t)a.m), n = own_sreg((int32_t)a.n), ncols = n + m;
   const int32_t sc = CD ? n : ncols;  // stored (priced) columns
-  const int64_t ld = w.ld;
-  const int32_t vw = (int32_t)w.vw;
+  const int64_t ld = own_sreg(w.ld);
+  const int32_t vw = own_sreg((int32_t)w.vw);
+  const int32_t cap_cap = own_sreg(w.cap_cap);
+  double* const Tm = own_sreg(w.T);  // constraint rows of the tableau
   const int64_t G = (int64_t)nb * NT;
   const int64_t gid = MAP == 0 ? (int64_t)tm.rank * NT + tid
                                : ((int64_t)(tid / 256) * nb + tm.rank) * 256 + (tid & 255);
@@ -223,15 +244,16 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   // index below e_static) follow the static grid-stride walk, which covers
   // the latency of the first tickets; the rest, in chunks of kChunkSteps x
   // NT vectors, go to whichever workgroup of the team asks next (atomic
-  // ticket counter), so that workgroups that run slower leave work to faster
-  // ones up to the end of the sweep.  Measured at 8192 x 8192 on 256
-  // workgroups, 3-step chunks beat 2 (the one counter's atomics become the
-  // limit) and 4..8 (coarser balance).
+  // ticket counters), so that workgroups that run slower leave work to
+  // faster ones up to the end of the sweep.  Measured at 8192 x 8192 on 256
+  // workgroups: with one counter, 3-step chunks beat 2 (that counter's
+  // atomics become the limit) and 4..8 (coarser balance); two counters make
+  // 2-step chunks the best.
   const int64_t e_total = (int64_t)m * vw;
   const int64_t steps_total = (e_total + G - 1) / G;
   // The dynamic part costs a few microseconds per pivot (ticket broadcasts,
   // the last chunk's latency); it only pays off on long sweeps.
-  const bool dyn = nb > 1 && steps_total >= kDynMinSteps;
+  const bool dyn = DYN && nb > 1 && steps_total >= kDynMinSteps;
   const int64_t e_static = dyn ? min((int64_t)kStaticSteps * G, e_total) : e_total;
   const int64_t chunk = (int64_t)kChunkSteps * NT;
   const uint32_t n_chunks = dyn ? (uint32_t)((e_total - e_static + chunk - 1) / chunk) : 0u;
@@ -302,11 +324,15 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       }
     }
 
-    // Zeroed whatever the team size: a resumable solve may be continued by a
-    // larger team in a later launch.
+    // Ticket counters reset (counter h to its first chunk, h) whatever the
+    // team size: a resumable solve may be continued by a larger team in a
+    // later launch.
     if (leader && tid == 0) {
-      __hip_atomic_store(w.tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(w.tickets + 32, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int h = 0; h < kTicketCounters; ++h) {
+        __hip_atomic_store(w.tickets + h * kTicketStride, (uint32_t)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w.tickets + h * kTicketStride + 32, (uint32_t)h, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     {
       Cand f0 = cand_none();
@@ -363,18 +389,21 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     ++done_here;
     uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
     if (tk && tid == 0) tk[0] = __builtin_amdgcn_s_memrealtime();
-    // The previous pivot's ticket counter is idle until the next pivot (every
-    // workgroup passed the last barrier after its final ticket): reset it.
+    // The previous pivot's ticket counters are idle until the next pivot
+    // (every workgroup passed the last barrier after its final ticket): reset
+    // them.
     if (dyn && leader && tid == 0)
-      __hip_atomic_store(w.tickets + 32 * ((iter + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int h = 0; h < kTicketCounters; ++h)
+        __hip_atomic_store(w.tickets + h * kTicketStride + 32 * ((iter + 1) & 1), (uint32_t)h, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     const int cur = (int)(iter & 1), nxt = cur ^ 1;
     double* obj_nxt = w.obj[nxt];
-    const double* rhs_cur = w.rhs[cur];
-    double* rhs_nxt = w.rhs[nxt];
-    const double* pcol_cur = w.pcol[cur];
-    double* pcol_nxt = w.pcol[nxt];
+    const double* rhs_cur = own_sreg(w.rhs[cur]);
+    double* rhs_nxt = own_sreg(w.rhs[nxt]);
+    const double* pcol_cur = own_sreg(w.pcol[cur]);
+    double* pcol_nxt = own_sreg(w.pcol[nxt]);
     double* pr_cur = w.pr[cur];
-    const dbl2* pr_prev = reinterpret_cast<const dbl2*>(w.pr[nxt]);
+    const dbl2* pr_prev = own_sreg(reinterpret_cast<const dbl2*>(w.pr[nxt]));
 
     // ---- P_t: Step 4 (pivot row / pivot, into LDS), Step 5 on the objective
     // row, Step 2 for the next pivot.  Row l's current content is the
@@ -467,12 +496,12 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       // Condensed: stored column kc becomes the leaving variable's column,
       // whose full-tableau entries before the pivot are 0 off row l.
       const int32_t kcv = kc >> 1, kch = kc & 1;
-      const double eps_p = a.eps_p;
+      const double eps_p = own_sreg(a.eps_p);
       const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
       // One element (i, v) of the dynamic part: the same work as one step of
       // the static walk below.
       auto element = [&](int32_t i, int32_t v) {
-        const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
+        const dbl2* rowp = reinterpret_cast<const dbl2*>(Tm) + (int64_t)i * ldv;
         const double f = gld(pcol_cur + i);
         const bool cap = (v == kv);
         double rh = 0.0;
@@ -497,8 +526,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
           gst(pcol_nxt + i, an);
           gst(rhs_nxt + i, rn);
-          const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
-          if (slot < w.cap_cap) {
+          const int32_t slot = cap_cap ? atomicAdd(cap_count, 1) : 0;
+          if (slot < cap_cap) {
             cap_a[slot] = an;
             cap_r[slot] = rn;
             cap_i[slot] = i;
@@ -508,20 +537,33 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         }
         if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
       };
-      // Two tickets are kept in flight per workgroup: both are requested
-      // before the static walk, and each is requested again as soon as the
-      // chunk it named has started, so an atomic's latency hides behind two
-      // chunks.  (This pivot's counter was reset a pivot ago.)  Requests of
-      // one thread to one counter are ordered, so tickets arrive increasing
-      // in the order they are used.
-      uint32_t* ctr = w.tickets + 32 * (iter & 1);
-      uint32_t tk_a = 0, tk_b = 0;
+      // Ticket counters: counter h holds the next chunk it hands out and
+      // steps by K (K = kTicketCounters): chunks h, h + K, h + 2K, ...  Each
+      // counter has its own 4 KiB block, so one counter's atomics do not
+      // bound the whole sweep.  A workgroup asks the first counter, from its
+      // home counter on, that has not run dry for it.  Thread 0 keeps a queue
+      // of two tickets: both are requested before the static walk, and a new
+      // one after this thread's first element of each chunk.  Tickets are
+      // used in the order they were requested; as one thread's requests to
+      // one counter are ordered, a ticket past the end means every later
+      // ticket of that counter is too.  (This pivot's counters were reset a
+      // pivot ago.)
+      uint32_t* ctr0 = w.tickets + 32 * (iter & 1);
+      const int home = tm.rank & (kTicketCounters - 1);
+      uint32_t dry = 0;  // bit h: counter h has run dry (thread 0)
+      auto request = [&]() -> uint32_t {
+        int h = home;
+        for (int j = 0; j < kTicketCounters && ((dry >> h) & 1u); ++j) h = (h + 1) & (kTicketCounters - 1);
+        return __hip_atomic_fetch_add(ctr0 + h * kTicketStride, (uint32_t)kTicketCounters, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+      };
+      uint32_t tq0 = 0, tq1 = 0;  // ticket queue, oldest first (thread 0)
       if (dyn && tid == 0) {
-        tk_a = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        tk_b = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tq0 = request();
+        tq1 = request();
       }
       int32_t i = i_start, v = v_start;
-      const dbl2* rowp = reinterpret_cast<const dbl2*>(w.T) + (int64_t)i * ldv;
+      const dbl2* rowp = reinterpret_cast<const dbl2*>(Tm) + (int64_t)i * ldv;
       const int64_t row_step = (int64_t)step_q * ldv;
       for (int64_t q = 0; q < n_static; ++q) {
         const double f = gld(pcol_cur + i);
@@ -552,8 +594,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
           gst(pcol_nxt + i, an);
           gst(rhs_nxt + i, rn);
-          const int32_t slot = w.cap_cap ? atomicAdd(cap_count, 1) : 0;
-          if (slot < w.cap_cap) {
+          const int32_t slot = cap_cap ? atomicAdd(cap_count, 1) : 0;
+          if (slot < cap_cap) {
             cap_a[slot] = an;
             cap_r[slot] = rn;
             cap_i[slot] = i;
@@ -572,22 +614,37 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         }
       }
       if (dyn) {
-        // Dynamic part of the sweep.  Ticket c covers flat elements
+        // Dynamic part of the sweep.  Chunk c covers flat elements
         // e_static + c * chunk + [0, chunk); thread tid takes every NT-th.
-        // `tkt` is the ticket register of this chunk; `par` selects the LDS
-        // slot that broadcasts it (two slots: the next chunk's write cannot
-        // overtake a slow reader of this one).
-        auto run_chunk = [&](uint32_t& tkt, int par) -> bool {
-          if (tid == 0) s_tk[par] = tkt;
+        // Thread 0 takes the oldest ticket and broadcasts it through one of
+        // two LDS slots (the next write cannot overtake a slow reader).  A
+        // ticket past the end marks its counter dry and is replaced, until a
+        // valid one comes or every counter is dry: then the ticket still in
+        // flight is past the end too.
+        constexpr uint32_t kAllDry = (1u << kTicketCounters) - 1u;
+        for (int par = 0;; par ^= 1) {
+          if (tid == 0) {
+            uint32_t c = n_chunks;
+            while (dry != kAllDry) {
+              const uint32_t t = tq0;
+              tq0 = tq1;
+              if (t < n_chunks) {
+                c = t;
+                break;
+              }
+              dry |= 1u << (t % (uint32_t)kTicketCounters);
+              if (dry != kAllDry) tq1 = request();
+            }
+            s_tk[par] = c;
+          }
           __syncthreads();
           const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_tk[par]);
-          if (c >= n_chunks) return false;
+          if (c >= n_chunks) break;
           const int64_t e0 = e_static + (int64_t)c * chunk + tid;
           int32_t ii = (int32_t)(e0 / vw), vv = (int32_t)(e0 % vw);
           for (int qq = 0; qq < kChunkSteps; ++qq) {
             if (ii < m) element(ii, vv);
-            if (qq == 0 && tid == 0)
-              tkt = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (qq == 0 && tid == 0) tq1 = request();
             vv += dq_r;
             ii += dq_q;
             if (vv >= vw) {
@@ -595,13 +652,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
               ++ii;
             }
           }
-          return true;
-        };
-        while (run_chunk(tk_a, 0) && run_chunk(tk_b, 1)) {
         }
       }
       __syncthreads();
-      const int32_t ncap = min(*cap_count, w.cap_cap);
+      const int32_t ncap = min(*cap_count, cap_cap);
       for (int32_t e = tid; e < ncap; e += NT) ratio_offer(rc, cap_a[e], cap_r[e], cap_i[e], eps_p);
     }
     rc = block_reduce(rc, scratch);
@@ -630,7 +684,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   if (status < 0) {
     // Suspended: keep the scalars for the next call (all workgroups agree).
     if (leader && tid == 0)
-      __hip_atomic_store(w.tickets + 32 * ((iter + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int h = 0; h < kTicketCounters; ++h)
+        __hip_atomic_store(w.tickets + h * kTicketStride + 32 * ((iter + 1) & 1), (uint32_t)h, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     if (CD && leader && tid == 0 && lprev >= 0) w.basis[lprev] = kprev;
     if (leader && tid == 0) {
       a.state->phase = 1;

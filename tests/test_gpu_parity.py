@@ -161,13 +161,16 @@ def test_paper_generator_instances(m, n, seed, schedule):
 @pytest.mark.parametrize("blocks,schedule", [(2, GRID), (3, GRID), (5, GRID), (2, CD), (3, CD)],
                          ids=["grid2", "grid3", "grid5", "condensed2", "condensed3"])
 def test_dynamic_sweep_bitwise(blocks, schedule):
-    """A sweep of at least 96 grid steps hands its tail out in chunks through
-    a ticket counter.  On a grid of a few workgroups a 700 x 1000 LP is long
-    enough for that; a chunk lost, done twice or taken from the wrong pivot's
-    counter would change bits, so the whole tableau must match the oracle."""
+    """A sweep of at least 48 grid steps hands all but its first 16 steps out
+    in chunks through two ticket counters (even and odd chunks); workgroups
+    of even and odd rank start on different counters and take from the other
+    once theirs runs dry.  On a grid of a few workgroups a 700 x 1000 LP is
+    long enough for that; a chunk lost, done twice or taken from the wrong
+    pivot's counter would change bits, so the whole tableau must match the
+    oracle."""
     m, n = 700, 1000
     vw = (n + 1) // 2 if schedule == CD else (n + m + 1) // 2
-    assert -(-m * vw // (blocks * 1024)) >= 96  # long enough for the ticket path
+    assert -(-m * vw // (blocks * 1024)) >= 48  # long enough for the ticket path
     A, b, c = lpgen.dense_lp(m, n, 11)
     announce(f"dynamic sweep {m}x{n} blocks={blocks} schedule={schedule}")
     g = gpu_solve(A, b, c, schedule=schedule, grid_blocks=blocks, want_tableau=True)
