@@ -153,6 +153,11 @@ typedef struct lpd_outputs {
  * lp_solve_dense_ex: solve one LP with options and optional outputs.
  * `prob`, `opt` and `out` are host structs read during the call; `opt` may be
  * NULL for defaults.  Same semantics, errors and ownership as lp_solve_dense.
+ * Sizes: LPD_SCHED_WORKGROUP needs the whole tableau in one workgroup's LDS
+ * (else LPD_ERR_TOO_LARGE); the grid schedules take any size whose workspace
+ * (about 8 (m+1)(n+m+1) bytes, or 8 (m+1)(n+1) condensed) fits in device
+ * memory (else LPD_ERR_OUT_OF_MEMORY): a pivot row longer than the LDS holds
+ * is swept in column panels, with the same results.
  */
 int lp_solve_dense_ex(const lpd_problem *prob, const lpd_options *opt, const lpd_outputs *out,
                       hipStream_t stream);
@@ -199,7 +204,10 @@ typedef struct lpd_batch_options {
  * LPs whose tableau fits in a wave's slice of LDS (wave_slots) are solved by
  * one wave each; others whose tableau fits in LDS by one workgroup in LDS;
  * larger ones by one workgroup over HBM, or by a team of workgroups if the
- * tableau is at least team_min_bytes.  Large LPs are started first.  Returns
+ * tableau is at least team_min_bytes.  Large LPs are started first.  Every
+ * LP's pivot row (n + m + 1 doubles, n + 1 condensed) must fit in LDS beside
+ * the reduction scratch: about 20,000 doubles on gfx950, else the call
+ * returns LPD_ERR_TOO_LARGE (lp_solve_dense_ex has no such limit).  Returns
  * LPD_SUCCESS or a negative lpd_error; asynchronous and stream-ordered like
  * lp_solve_dense.  Host arrays are only read during the call.
  */
@@ -292,7 +300,8 @@ lpd_server *lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
  * until the completion of this request has been returned by lpd_server_poll.
  * Returns the request id (> 0), or a negative lpd_error: LPD_ERR_INVALID_ARG
  * (m or n < 1), LPD_ERR_NULL_POINTER, LPD_ERR_SIZE_OVERFLOW,
- * LPD_ERR_TOO_LARGE (footprint above the whole budget), LPD_ERR_NOT_FOUND
+ * LPD_ERR_TOO_LARGE (footprint above the whole budget, or a pivot row
+ * longer than lp_solve_batch takes), LPD_ERR_NOT_FOUND
  * (null or stopping server).  Thread-safe. */
 int64_t lpd_server_submit(lpd_server *server, int64_t m, int64_t n, const double *A, const double *b,
                           const double *c, double *x_out);

@@ -365,6 +365,10 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
                                     (unsigned)P.lds_bytes, stream);
 }
 
+bool batch_row_fits(int64_t m, int64_t n, bool condensed, size_t lds_limit) {
+  return kScratchBytes + (size_t)grid_layout(m, n, 1, condensed).vw * 16 + 16 <= lds_limit;
+}
+
 int batch_max_blocks(size_t lds_bytes, bool condensed) {
   const void* fn = condensed ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>;
   int dev = 0, ncu = 0, per_cu = 0;

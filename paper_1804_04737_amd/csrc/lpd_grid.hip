@@ -8,12 +8,12 @@
 namespace lpd {
 namespace {
 
-template <int NT, int MAP, bool CD = false>
+template <int NT, int MAP, bool CD = false, bool PN = false>
 __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   uint32_t epoch = 0;
   const Team tm{(int)blockIdx.x, (int)gridDim.x, w.slots, &epoch};
-  team_solve<NT, MAP, CD>(a, w, tm, smem);
+  team_solve<NT, MAP, CD, true, PN>(a, w, tm, smem);
 }
 
 // Clears the barrier slots of a fresh workspace (stream-ordered, no memset node).
@@ -30,9 +30,10 @@ constexpr GridKernel kVariants[] = {grid_solve_kernel<kNT, 0>, grid_solve_kernel
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 // Condensed tableau (nonbasic columns only).
 constexpr GridKernel kCondensed = grid_solve_kernel<kNT, 0, true>;
+// Pivot rows longer than the LDS holds: the sweep runs over column panels.
+constexpr GridKernel kPanelled = grid_solve_kernel<kNT, 0, false, true>;
+constexpr GridKernel kPanelledCondensed = grid_solve_kernel<kNT, 0, true, true>;
 
-
-// LPD_GRID_VARIANT (tuning / diagnostics) picks a kernel variant.
 // LPD_GRID_VARIANT (tuning / diagnostics) picks the thread mapping; 0 by default.
 int variant_index(int64_t) {
   const char* e = getenv("LPD_GRID_VARIANT");
@@ -40,7 +41,10 @@ int variant_index(int64_t) {
   return (x >= 0 && x < kNumVariants) ? x : 0;
 }
 
-GridKernel pick_kernel(int64_t vw, bool condensed) { return condensed ? kCondensed : kVariants[variant_index(vw)]; }
+GridKernel pick_kernel(int64_t vw, bool condensed, bool panelled) {
+  if (panelled) return condensed ? kPanelledCondensed : kPanelled;
+  return condensed ? kCondensed : kVariants[variant_index(vw)];
+}
 
 int lds_limit() {
   int dev = 0, lds_max = 0;
@@ -51,33 +55,51 @@ int lds_limit() {
 
 // LDS plan of the grid kernel: reduction scratch, the normalised pivot row
 // (vw 16-byte vectors) and a capture list of up to kCapMax entries, shrunk to
-// what the LDS leaves.  Returns 0 if the pivot row alone does not fit.
-size_t lds_plan(int64_t m, int64_t n, int32_t* cap, bool condensed) {
+// what the LDS leaves.  A pivot row that does not fit with a full capture
+// list is held one panel at a time: *vecs (the LDS row buffer, in vectors)
+// is then below vw, a multiple of 64, with room for a full capture list.
+// Returns 0 if even that does not fit.
+size_t lds_plan(int64_t m, int64_t n, int32_t* cap, int32_t* vecs, bool condensed) {
   const int64_t vw = grid_layout(m, n, 1, condensed).vw;
-  const size_t base = kScratchBytes + (size_t)vw * 16 + 16;
   const size_t limit = (size_t)lds_limit();
-  if (base > limit) return 0;
-  const size_t c = std::min<size_t>(kCapMax, (limit - base) / kCapEntryBytes);
+  const size_t fixed = kScratchBytes + 16;
+  const size_t full_cap = (size_t)kCapMax * kCapEntryBytes;
+  size_t c;
+  int64_t v;
+  if (fixed + (size_t)vw * 16 + full_cap <= limit) {
+    v = vw;
+    c = kCapMax;
+  } else if (fixed + (size_t)vw * 16 <= limit && (limit - fixed - (size_t)vw * 16) / kCapEntryBytes >= 256) {
+    // The whole row fits with a shorter capture list (overflow is handled).
+    v = vw;
+    c = std::min<size_t>(kCapMax, (limit - fixed - (size_t)vw * 16) / kCapEntryBytes);
+  } else {
+    if (limit < fixed + full_cap + 64 * 16) return 0;
+    v = (int64_t)((limit - fixed - full_cap) / 16) / 64 * 64;
+    c = kCapMax;
+  }
   *cap = (int32_t)c;
-  return base + c * kCapEntryBytes;
+  *vecs = (int32_t)v;
+  return fixed + (size_t)v * 16 + c * kCapEntryBytes;
 }
 
 }  // namespace
 
 size_t grid_lds_bytes(int64_t m, int64_t n, int /*nthreads*/, bool condensed) {
-  int32_t cap = 0;
-  return lds_plan(m, n, &cap, condensed);
+  int32_t cap = 0, vecs = 0;
+  return lds_plan(m, n, &cap, &vecs, condensed);
 }
 
 int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed) {
   (void)nthreads;
-  int32_t cap = 0;
-  const size_t lds = lds_plan(m, n, &cap, condensed);
+  int32_t cap = 0, vecs = 0;
+  const size_t lds = lds_plan(m, n, &cap, &vecs, condensed);
   if (lds == 0) return 0;
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  auto fn = pick_kernel(grid_layout(m, n, 1, condensed).vw, condensed);
+  const int64_t vw = grid_layout(m, n, 1, condensed).vw;
+  auto fn = pick_kernel(vw, condensed, vecs < vw);
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0;
@@ -90,8 +112,7 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
   (void)nthreads;
   const GridLayout L = grid_layout(a.m, a.n, nblocks, condensed);
   GridWork w = make_grid_work(L, a.m, workspace);
-  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap, condensed);
-  w.lds_vecs = (int32_t)L.vw;
+  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap, &w.lds_vecs, condensed);
   if (lds == 0) return hipErrorInvalidValue;
 
   const int nslots = 2 * nblocks;
@@ -99,7 +120,7 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  auto fn = pick_kernel(L.vw, condensed);
+  auto fn = pick_kernel(L.vw, condensed, w.lds_vecs < L.vw);
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   SolveArgs args = a;

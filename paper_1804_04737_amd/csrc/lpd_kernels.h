@@ -80,7 +80,7 @@ struct GridWork {
   uint32_t* tickets;   // sweep chunk tickets: counter h of pivot parity q at [h * kTicketStride + 32 q]
   BarrierSlot* slots; // 2 * nblocks
   int32_t cap_cap;     // capacity of the LDS capture list (entries)
-  int32_t lds_vecs;    // capacity of the LDS pivot-row buffer (16-byte vectors, >= vw)
+  int32_t lds_vecs;    // capacity of the LDS pivot-row buffer (16-byte vectors; < vw: column panels)
 };
 
 // Sizes of the grid workspace pieces (bytes, each rounded to 256).

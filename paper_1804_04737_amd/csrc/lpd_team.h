@@ -209,7 +209,11 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 // leader would otherwise write it): the row of the previous pivot holds kprev.
 // DYN = false compiles the dynamic sweep out (for callers whose teams are
 // always one workgroup, which never use it).
-template <int NT, int MAP, bool CD = false, bool DYN = true>
+// PN = true is for pivot rows longer than the LDS holds (w.lds_vecs < vw):
+// the sweep runs over column panels of w.lds_vecs vectors, panel after
+// panel, and a workgroup forms the panel of the normalised pivot row it
+// needs from the pivot row itself (same division as in P, so the same bits).
+template <int NT, int MAP, bool CD = false, bool DYN = true, bool PN = false>
 __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm, unsigned char* smem) {
   Cand* scratch = reinterpret_cast<Cand*>(smem);
   dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
@@ -256,7 +260,15 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const bool dyn = DYN && nb > 1 && steps_total >= kDynMinSteps;
   const int64_t e_static = dyn ? min((int64_t)kStaticSteps * G, e_total) : e_total;
   const int64_t chunk = (int64_t)kChunkSteps * NT;
-  const uint32_t n_chunks = dyn ? (uint32_t)((e_total - e_static + chunk - 1) / chunk) : 0u;
+  // Panels (PN): full panels of pvw vectors and a last one of pw_last; a
+  // chunk never straddles two panels.
+  const int32_t pvw = PN ? w.lds_vecs : vw;
+  const int32_t npan = PN ? (vw + pvw - 1) / pvw : 1;
+  const int32_t pw_last = vw - (npan - 1) * pvw;
+  const int64_t cpp = ((int64_t)m * pvw + chunk - 1) / chunk;  // chunks per full panel
+  const uint32_t n_chunks =
+      PN ? (uint32_t)((int64_t)(npan - 1) * cpp + ((int64_t)m * pw_last + chunk - 1) / chunk)
+         : (dyn ? (uint32_t)((e_total - e_static + chunk - 1) / chunk) : 0u);
   const int64_t n_static = e_static > gid ? (e_static - gid - 1) / G + 1 : 0;
   const int32_t dq_q = (int32_t)(NT / vw), dq_r = (int32_t)(NT % vw);
 
@@ -429,7 +441,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         on.x = __builtin_fma(-g, r.x, o.x);
         on.y = __builtin_fma(-g, r.y, o.y);
       }
-      prow[v] = r;
+      if constexpr (!PN) prow[v] = r;
       // Each workgroup publishes one slice of the new rows (all copies agree).
       if (v >= pub_v0 && v < pub_v1) {
         gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on);
@@ -500,6 +512,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
       // One element (i, v) of the dynamic part: the same work as one step of
       // the static walk below.
+      int32_t pv0 = 0;  // first vector of the panel in LDS (PN)
       auto element = [&](int32_t i, int32_t v) {
         const dbl2* rowp = reinterpret_cast<const dbl2*>(Tm) + (int64_t)i * ldv;
         const double f = gld(pcol_cur + i);
@@ -513,7 +526,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           if (kch) t.y = 0.0;
           else t.x = 0.0;
         }
-        const dbl2 r = prow[v];
+        const dbl2 r = prow[PN ? v - pv0 : v];
         dbl2 nv;
         if (i == l) {
           nv = r;
@@ -562,94 +575,166 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         tq0 = request();
         tq1 = request();
       }
-      int32_t i = i_start, v = v_start;
-      const dbl2* rowp = reinterpret_cast<const dbl2*>(Tm) + (int64_t)i * ldv;
-      const int64_t row_step = (int64_t)step_q * ldv;
-      for (int64_t q = 0; q < n_static; ++q) {
-        const double f = gld(pcol_cur + i);
-        const bool cap = (v == kv);
-        double rh = 0.0;
-        if (cap) rh = gld(rhs_cur + i);
-        const dbl2* src = (i == lprev) ? pr_prev : rowp;
-        dbl2 t;
-        if (i != l) t = ld_stream(src + v);
-        if (CD && v == kcv) {
-          if (kch) t.y = 0.0;
-          else t.x = 0.0;
-        }
-        const dbl2 r = prow[v];
-        dbl2 nv;
-        if (i == l) {
-          nv = r;
-        } else {
-          nv.x = __builtin_fma(-f, r.x, t.x);
-          nv.y = __builtin_fma(-f, r.y, t.y);
-        }
-        // The capture runs before this element's store is issued: waiting on
-        // its operands must not also wait for the store to complete.
-        if (cap) {
-          // New entering-column entry and right-hand side of row i; the ratio
-          // itself is formed after the sweep by the whole workgroup.
-          const double an = kh ? nv.y : nv.x;
-          const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
-          gst(pcol_nxt + i, an);
-          gst(rhs_nxt + i, rn);
-          const int32_t slot = cap_cap ? atomicAdd(cap_count, 1) : 0;
-          if (slot < cap_cap) {
-            cap_a[slot] = an;
-            cap_r[slot] = rn;
-            cap_i[slot] = i;
-          } else {
-            ratio_offer(rc, an, rn, i, eps_p);
-          }
-        }
-        if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
-        v += step_r;
-        i += step_q;
-        rowp += row_step;
-        if (v >= vw) {
-          v -= vw;
-          ++i;
-          rowp += ldv;
-        }
-      }
-      if (dyn) {
-        // Dynamic part of the sweep.  Chunk c covers flat elements
-        // e_static + c * chunk + [0, chunk); thread tid takes every NT-th.
-        // Thread 0 takes the oldest ticket and broadcasts it through one of
-        // two LDS slots (the next write cannot overtake a slow reader).  A
-        // ticket past the end marks its counter dry and is replaced, until a
-        // valid one comes or every counter is dry: then the ticket still in
-        // flight is past the end too.
+      if constexpr (PN) {
+        // Panel-major sweep.  Chunk c: panel pp = c / cpp (the last panel
+        // takes the rest), elements [lc * chunk, (lc + 1) * chunk) of the
+        // panel's m x pw block in row-major order.  Chunks come from the
+        // tickets on long sweeps, else in the static order rank, rank + nb, ...
         constexpr uint32_t kAllDry = (1u << kTicketCounters) - 1u;
+        int32_t loaded = -1;
+        uint32_t jst = 0;
         for (int par = 0;; par ^= 1) {
-          if (tid == 0) {
-            uint32_t c = n_chunks;
-            while (dry != kAllDry) {
-              const uint32_t t = tq0;
-              tq0 = tq1;
-              if (t < n_chunks) {
-                c = t;
-                break;
+          uint32_t c;
+          if (dyn) {
+            if (tid == 0) {
+              uint32_t cn = n_chunks;
+              while (dry != kAllDry) {
+                const uint32_t t = tq0;
+                tq0 = tq1;
+                if (t < n_chunks) {
+                  cn = t;
+                  break;
+                }
+                dry |= 1u << (t % (uint32_t)kTicketCounters);
+                if (dry != kAllDry) tq1 = request();
               }
-              dry |= 1u << (t % (uint32_t)kTicketCounters);
-              if (dry != kAllDry) tq1 = request();
+              s_tk[par] = cn;
             }
-            s_tk[par] = c;
+            __syncthreads();
+            c = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_tk[par]);
+          } else {
+            c = (uint32_t)tm.rank + jst * (uint32_t)nb;
+            ++jst;
           }
-          __syncthreads();
-          const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_tk[par]);
           if (c >= n_chunks) break;
-          const int64_t e0 = e_static + (int64_t)c * chunk + tid;
-          int32_t ii = (int32_t)(e0 / vw), vv = (int32_t)(e0 % vw);
+          const int32_t pp = (int64_t)c < (int64_t)(npan - 1) * cpp ? (int32_t)(c / cpp) : npan - 1;
+          const int64_t lc = (int64_t)c - (int64_t)pp * cpp;
+          const int32_t pw = pp < npan - 1 ? pvw : pw_last;
+          if (pp != loaded) {
+            // Normalised pivot row, vectors [pp * pvw, pp * pvw + pw), into
+            // LDS.  Row l is read-only during the sweep (as in P).
+            __syncthreads();
+            pv0 = pp * pvw;
+            for (int32_t u = tid; u < pw; u += NT) {
+              const int32_t vq = pv0 + u;
+              const dbl2 tr = gld2(rowl + vq);
+              dbl2 r;
+              if constexpr (CD) {
+                r.x = 2 * vq == kc ? 1.0 / p : tr.x / p;
+                r.y = 2 * vq + 1 == kc ? 1.0 / p : tr.y / p;
+              } else {
+                r.x = tr.x / p;
+                r.y = tr.y / p;
+              }
+              prow[u] = r;
+            }
+            __syncthreads();
+            loaded = pp;
+          }
+          const int64_t e0 = lc * chunk + tid;
+          int32_t ii = (int32_t)(e0 / pw), vv = (int32_t)(e0 % pw);
+          const int32_t pq = NT / pw, pr = NT % pw;
           for (int qq = 0; qq < kChunkSteps; ++qq) {
-            if (ii < m) element(ii, vv);
-            if (qq == 0 && tid == 0) tq1 = request();
-            vv += dq_r;
-            ii += dq_q;
-            if (vv >= vw) {
-              vv -= vw;
+            if (ii < m) element(ii, pv0 + vv);
+            if (dyn && qq == 0 && tid == 0) tq1 = request();
+            vv += pr;
+            ii += pq;
+            if (vv >= pw) {
+              vv -= pw;
               ++ii;
+            }
+          }
+        }
+      } else {
+        int32_t i = i_start, v = v_start;
+        const dbl2* rowp = reinterpret_cast<const dbl2*>(Tm) + (int64_t)i * ldv;
+        const int64_t row_step = (int64_t)step_q * ldv;
+        for (int64_t q = 0; q < n_static; ++q) {
+          const double f = gld(pcol_cur + i);
+          const bool cap = (v == kv);
+          double rh = 0.0;
+          if (cap) rh = gld(rhs_cur + i);
+          const dbl2* src = (i == lprev) ? pr_prev : rowp;
+          dbl2 t;
+          if (i != l) t = ld_stream(src + v);
+          if (CD && v == kcv) {
+            if (kch) t.y = 0.0;
+            else t.x = 0.0;
+          }
+          const dbl2 r = prow[v];
+          dbl2 nv;
+          if (i == l) {
+            nv = r;
+          } else {
+            nv.x = __builtin_fma(-f, r.x, t.x);
+            nv.y = __builtin_fma(-f, r.y, t.y);
+          }
+          // The capture runs before this element's store is issued: waiting on
+          // its operands must not also wait for the store to complete.
+          if (cap) {
+            // New entering-column entry and right-hand side of row i; the ratio
+            // itself is formed after the sweep by the whole workgroup.
+            const double an = kh ? nv.y : nv.x;
+            const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
+            gst(pcol_nxt + i, an);
+            gst(rhs_nxt + i, rn);
+            const int32_t slot = cap_cap ? atomicAdd(cap_count, 1) : 0;
+            if (slot < cap_cap) {
+              cap_a[slot] = an;
+              cap_r[slot] = rn;
+              cap_i[slot] = i;
+            } else {
+              ratio_offer(rc, an, rn, i, eps_p);
+            }
+          }
+          if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
+          v += step_r;
+          i += step_q;
+          rowp += row_step;
+          if (v >= vw) {
+            v -= vw;
+            ++i;
+            rowp += ldv;
+          }
+        }
+        if (dyn) {
+          // Dynamic part of the sweep.  Chunk c covers flat elements
+          // e_static + c * chunk + [0, chunk); thread tid takes every NT-th.
+          // Thread 0 takes the oldest ticket and broadcasts it through one of
+          // two LDS slots (the next write cannot overtake a slow reader).  A
+          // ticket past the end marks its counter dry and is replaced, until a
+          // valid one comes or every counter is dry: then the ticket still in
+          // flight is past the end too.
+          constexpr uint32_t kAllDry = (1u << kTicketCounters) - 1u;
+          for (int par = 0;; par ^= 1) {
+            if (tid == 0) {
+              uint32_t c = n_chunks;
+              while (dry != kAllDry) {
+                const uint32_t t = tq0;
+                tq0 = tq1;
+                if (t < n_chunks) {
+                  c = t;
+                  break;
+                }
+                dry |= 1u << (t % (uint32_t)kTicketCounters);
+                if (dry != kAllDry) tq1 = request();
+              }
+              s_tk[par] = c;
+            }
+            __syncthreads();
+            const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_tk[par]);
+            if (c >= n_chunks) break;
+            const int64_t e0 = e_static + (int64_t)c * chunk + tid;
+            int32_t ii = (int32_t)(e0 / vw), vv = (int32_t)(e0 % vw);
+            for (int qq = 0; qq < kChunkSteps; ++qq) {
+              if (ii < m) element(ii, vv);
+              if (qq == 0 && tid == 0) tq1 = request();
+              vv += dq_r;
+              ii += dq_q;
+              if (vv >= vw) {
+                vv -= vw;
+                ++ii;
+              }
             }
           }
         }

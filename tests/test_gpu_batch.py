@@ -108,6 +108,16 @@ def test_batch_with_edge_cases(wave_slots):
         assert np.array_equal(bits(xs[i]), bits(ref.x))
 
 
+def test_batch_rejects_rows_longer_than_lds():
+    """A batch walks each LP with its pivot row in LDS (no column panels):
+    an LP whose row does not fit is refused before anything is launched."""
+    announce("batch with a 10 x 25000 LP")
+    lps = [lpgen.dense_lp(20, 30, 1), lpgen.dense_lp(10, 25000, 2)]
+    with pytest.raises(lpdense.LpdError) as e:
+        _run_batch(lps)
+    assert e.value.code == -7
+
+
 def test_batch_max_iter_applies_to_each_lp():
     lps = _mixed_lps(3, count=12) + _tiny_lps(3, count=12)
     announce("batch max_iter=5")

@@ -126,6 +126,10 @@ def test_server_rejects_and_edge_cases():
         with pytest.raises(lpdense.LpdError) as e:
             tiny.submit(*lpgen.dense_lp(400, 500, 1))   # footprint above the whole budget
         assert e.value.code == -7
+    with lpdense.Server(1 << 32) as wide:
+        with pytest.raises(lpdense.LpdError) as e:
+            wide.submit(*lpgen.dense_lp(10, 25000, 1))  # pivot row longer than the LDS holds
+        assert e.value.code == -7
     with lpdense.Server(1 << 30, pivots_per_epoch=4, max_iter=7) as srv:
         ids = [srv.submit(*lp) for lp in lps]
         got = _drain(srv, len(ids))
