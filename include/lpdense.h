@@ -204,10 +204,11 @@ typedef struct lpd_batch_options {
  * LPs whose tableau fits in a wave's slice of LDS (wave_slots) are solved by
  * one wave each; others whose tableau fits in LDS by one workgroup in LDS;
  * larger ones by one workgroup over HBM, or by a team of workgroups if the
- * tableau is at least team_min_bytes.  Large LPs are started first.  Every
- * LP's pivot row (n + m + 1 doubles, n + 1 condensed) must fit in LDS beside
- * the reduction scratch: about 20,000 doubles on gfx950, else the call
- * returns LPD_ERR_TOO_LARGE (lp_solve_dense_ex has no such limit).  Returns
+ * tableau is at least team_min_bytes.  Large LPs are started first.  An LP
+ * whose pivot row (n + m + 1 doubles, n + 1 condensed) does not fit in LDS
+ * beside the reduction scratch (about 20,000 doubles on gfx950) is solved
+ * after the batched launch, alone on the grid schedule (as lp_solve_dense_ex,
+ * same results), on the same stream.  Returns
  * LPD_SUCCESS or a negative lpd_error; asynchronous and stream-ordered like
  * lp_solve_dense.  Host arrays are only read during the call.
  */

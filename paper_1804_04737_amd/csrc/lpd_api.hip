@@ -152,6 +152,46 @@ int hip_err(hipError_t e) {
   return LPD_ERR_HIP;
 }
 
+// One batched launch over the LPs `idx` (indices into the caller's arrays).
+int run_batch(BatchPlan& P, const std::vector<int32_t>& idx, const int64_t* m, const int64_t* n,
+              const double* A_pack, const int64_t* A_off, const double* b_pack, const int64_t* b_off,
+              const double* c_pack, const int64_t* c_off, double* x_pack, const int64_t* x_off, double* obj,
+              int32_t* status, int64_t* iterations, double eps_d, double eps_p, int64_t max_iter,
+              hipStream_t stream) {
+  const int32_t count = (int32_t)idx.size();
+  std::vector<BatchItem> items((size_t)count);
+  for (int32_t j = 0; j < count; ++j) {
+    const int32_t i = idx[(size_t)j];
+    SolveArgs& a = items[(size_t)j].a;
+    a.m = m[i];
+    a.n = n[i];
+    a.A = A_pack + A_off[i];
+    a.b = b_pack + b_off[i];
+    a.c = c_pack + c_off[i];
+    a.eps_d = eps_d;
+    a.eps_p = eps_p;
+    a.max_iter = max_iter >= 0 ? max_iter : 50 * (m[i] + n[i]);
+    a.x = x_pack + x_off[i];
+    a.obj = obj + i;
+    a.status = status + i;
+    a.iterations = iterations ? iterations + i : nullptr;
+    items[(size_t)j].klass = P.klass[(size_t)j];
+    items[(size_t)j].tclass = P.tclass[(size_t)j];
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && P.total > total_b) return LPD_ERR_OUT_OF_MEMORY;
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, P.total, stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hip_err(e);
+  }
+  e = launch_batch(P, items, ws, stream);
+  const hipError_t ef = hipFreeAsync(ws, stream);
+  if (e != hipSuccess) return hip_err(e);
+  return hip_err(ef);
+}
+
 }  // namespace
 
 BatchKnobs tuned_batch_knobs() {
@@ -290,42 +330,46 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
   knobs.wave_slots = wave_slots > 0 ? wave_slots : (wave_slots < 0 ? 0 : tuning().wave_slots);
   knobs.condensed = condensed;
 
-  BatchPlan P = plan_batch(count, m, n, knobs, nblocks);
-  if (!P.ok) return LPD_ERR_TOO_LARGE;
-  const int maxb = batch_max_blocks(P.lds_bytes, P.condensed);
-  if (maxb <= 0) return LPD_ERR_TOO_LARGE;
-  if (nblocks > maxb) P = plan_batch(count, m, n, knobs, maxb);
-
-  std::vector<BatchItem> items((size_t)count);
-  for (int32_t i = 0; i < count; ++i) {
-    SolveArgs& a = items[(size_t)i].a;
-    a.m = m[i];
-    a.n = n[i];
-    a.A = A_pack + A_off[i];
-    a.b = b_pack + b_off[i];
-    a.c = c_pack + c_off[i];
-    a.eps_d = eps_d;
-    a.eps_p = eps_p;
-    a.max_iter = max_iter >= 0 ? max_iter : 50 * (m[i] + n[i]);
-    a.x = x_pack + x_off[i];
-    a.obj = obj + i;
-    a.status = status + i;
-    a.iterations = iterations ? iterations + i : nullptr;
-    items[(size_t)i].klass = P.klass[(size_t)i];
-    items[(size_t)i].tclass = P.tclass[(size_t)i];
+  // LPs the batch kernel cannot place (pivot row longer than the LDS holds)
+  // are solved after the batch, one at a time on the grid schedule with its
+  // column panels, on the same stream: the same results as in the batch.
+  const size_t lds_total = (size_t)batch_lds_total();
+  std::vector<int32_t> in_batch, alone;
+  for (int32_t i = 0; i < count; ++i)
+    (batch_can_place(m[i], n[i], condensed, lds_total) ? in_batch : alone).push_back(i);
+  const int32_t nbat = (int32_t)in_batch.size();
+  std::vector<int64_t> mb((size_t)nbat), nbv((size_t)nbat);
+  for (int32_t j = 0; j < nbat; ++j) {
+    mb[(size_t)j] = m[in_batch[(size_t)j]];
+    nbv[(size_t)j] = n[in_batch[(size_t)j]];
   }
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && P.total > total_b) return LPD_ERR_OUT_OF_MEMORY;
-  void* ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, P.total, stream);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return hip_err(e);
+  if (nbat > 0) {
+    BatchPlan P = plan_batch(nbat, mb.data(), nbv.data(), knobs, nblocks);
+    if (!P.ok) return LPD_ERR_TOO_LARGE;
+    const int maxb = batch_max_blocks(P.lds_bytes, P.condensed);
+    if (maxb <= 0) return LPD_ERR_TOO_LARGE;
+    if (nblocks > maxb) P = plan_batch(nbat, mb.data(), nbv.data(), knobs, maxb);
+    rc = run_batch(P, in_batch, m, n, A_pack, A_off, b_pack, b_off, c_pack, c_off, x_pack, x_off, obj, status,
+                   iterations, eps_d, eps_p, max_iter, stream);
+    if (rc != LPD_SUCCESS) return rc;
   }
-  e = launch_batch(P, items, ws, stream);
-  const hipError_t ef = hipFreeAsync(ws, stream);
-  if (e != hipSuccess) return hip_err(e);
-  return hip_err(ef);
+  for (int32_t i : alone) {
+    lpd_problem pr{m[i], n[i], A_pack + A_off[i], b_pack + b_off[i], c_pack + c_off[i]};
+    lpd_options o{};
+    o.eps_d = eps_d;
+    o.eps_p = eps_p;
+    o.max_iter = max_iter;
+    o.schedule = condensed ? LPD_SCHED_GRID_CONDENSED : LPD_SCHED_GRID;
+    o.grid_blocks = opt ? opt->grid_blocks : 0;
+    lpd_outputs out{};
+    out.x = x_pack + x_off[i];
+    out.obj = obj + i;
+    out.status = status + i;
+    out.iterations = iterations ? iterations + i : nullptr;
+    rc = lp_solve_dense_ex(&pr, &o, &out, stream);
+    if (rc != LPD_SUCCESS) return rc;
+  }
+  return LPD_SUCCESS;
 }
 
 uint64_t lpd_workspace_bytes(int64_t m, int64_t n) {

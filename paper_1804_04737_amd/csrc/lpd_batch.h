@@ -101,10 +101,13 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
 int batch_max_blocks(size_t lds_bytes, bool condensed = false);
 // Knobs from the autotune table (built-in defaults when there is none).
 BatchKnobs tuned_batch_knobs();
-// Whether an LP that a batch walks over HBM (not LDS-resident) can run: its
-// pivot row must fit in LDS beside the reduction scratch (the batch kernel
-// has no column panels).
-bool batch_row_fits(int64_t m, int64_t n, bool condensed, size_t lds_limit);
+// LDS per workgroup (bytes) of the current device, as the planner uses it.
+int batch_lds_total();
+// Whether the batch kernel can place an LP (lds_total: the device's LDS per
+// workgroup): its tableau fits in the planner's LDS budget, or, walked over
+// HBM, its pivot row does beside the reduction scratch (the batch kernel has
+// no column panels).
+bool batch_can_place(int64_t m, int64_t n, bool condensed, size_t lds_total);
 // Tableau bytes of an m x n LP and the bytes one grid-walk workspace needs.
 inline double tableau_bytes(int64_t m, int64_t n) { return ((double)m + 1) * (double)(n + m + 1) * 8.0; }
 // Bytes of the tableau a grid walk stores and streams: the full one, or only

@@ -365,8 +365,14 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
                                     (unsigned)P.lds_bytes, stream);
 }
 
-bool batch_row_fits(int64_t m, int64_t n, bool condensed, size_t lds_limit) {
-  return kScratchBytes + (size_t)grid_layout(m, n, 1, condensed).vw * 16 + 16 <= lds_limit;
+int batch_lds_total() { return lds_limit_bytes(); }
+
+bool batch_can_place(int64_t m, int64_t n, bool condensed, size_t lds_total) {
+  // Same budget as plan_batch: the kernel's static LDS and alignment slack
+  // stay outside it.
+  const size_t limit = lds_total > 256 ? lds_total - 256 : 0;
+  if (wg_lds_bytes(m, n) <= limit) return true;
+  return kScratchBytes + (size_t)grid_layout(m, n, 1, condensed).vw * 16 + 16 <= limit;
 }
 
 int batch_max_blocks(size_t lds_bytes, bool condensed) {

@@ -410,8 +410,8 @@ int64_t lpd_server_submit(lpd_server* s, int64_t m, int64_t n, const double* A, 
   if (m > (1 << 30) || n > (1 << 30) || m + n + 1 > (1 << 30)) return LPD_ERR_SIZE_OVERFLOW;
   // Same LDS tests as the batch planner: an LP it could not place would fail
   // the whole epoch, so it is refused here.
+  if (!batch_can_place(m, n, s->knobs.condensed, s->lds_limit)) return LPD_ERR_TOO_LARGE;
   const bool lds = wg_lds_bytes(m, n) + 256 <= s->lds_limit;
-  if (!lds && !batch_row_fits(m, n, s->knobs.condensed, (size_t)s->lds_limit)) return LPD_ERR_TOO_LARGE;
   const uint64_t f = footprint_of(m, n, lds, s->knobs.condensed);
   if (f > s->budget) return LPD_ERR_TOO_LARGE;
   Request r;

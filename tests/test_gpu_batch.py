@@ -108,14 +108,21 @@ def test_batch_with_edge_cases(wave_slots):
         assert np.array_equal(bits(xs[i]), bits(ref.x))
 
 
-def test_batch_rejects_rows_longer_than_lds():
-    """A batch walks each LP with its pivot row in LDS (no column panels):
-    an LP whose row does not fit is refused before anything is launched."""
-    announce("batch with a 10 x 25000 LP")
-    lps = [lpgen.dense_lp(20, 30, 1), lpgen.dense_lp(10, 25000, 2)]
-    with pytest.raises(lpdense.LpdError) as e:
-        _run_batch(lps)
-    assert e.value.code == -7
+@pytest.mark.parametrize("full", [False, True], ids=["condensed", "full"])
+def test_batch_with_rows_longer_than_lds(full):
+    """The batch kernel walks each LP with its pivot row in LDS.  LPs whose
+    row does not fit (10 x 25000, 6 x 40000) are solved after the batch on
+    the grid schedule with column panels; every result, theirs included,
+    equals the oracle's bits."""
+    lps = [lpgen.dense_lp(20, 30, 1), lpgen.dense_lp(10, 25000, 2), lpgen.dense_lp(300, 200, 3),
+           lpgen.dense_lp(6, 40000, 4), lpgen.dense_lp(64, 64, 5)]
+    announce(f"batch with rows longer than the LDS full_tableau={full}")
+    xs, obj, st, it = _run_batch(lps, full_tableau=full)
+    for i, (A, b, c) in enumerate(lps):
+        ref = oracle.solve(A, b, c)
+        assert st[i] == ref.status and it[i] == ref.iterations, (i, st[i], ref.status)
+        assert np.array_equal(bits(xs[i]), bits(ref.x)), i
+        assert bits([obj[i]])[0] == bits([ref.obj])[0], i
 
 
 def test_batch_max_iter_applies_to_each_lp():
