@@ -226,7 +226,9 @@ int lp_solve_batch(int32_t count, const int64_t *m, const int64_t *n, const doub
  * The worker repeats epochs: admit what fits, then run one batched launch
  * (the schedule of lp_solve_batch) in which every resident LP advances by at
  * most `pivots_per_epoch` pivots, its tableau staying in HBM between epochs
- * (an LP whose tableau fits in LDS is solved to the end within one epoch).
+ * (an LP whose tableau fits in LDS is solved to the end within one epoch;
+ * an LP whose pivot row is longer than lp_solve_batch can batch gets a grid
+ * launch of its own in each epoch, after the batched one).
  * LPs that finished leave, their memory returns to the budget and their
  * completion is queued.  Requests that arrive while others run therefore
  * share the device with them.  Each LP performs exactly the pivots of its own
@@ -301,8 +303,7 @@ lpd_server *lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
  * until the completion of this request has been returned by lpd_server_poll.
  * Returns the request id (> 0), or a negative lpd_error: LPD_ERR_INVALID_ARG
  * (m or n < 1), LPD_ERR_NULL_POINTER, LPD_ERR_SIZE_OVERFLOW,
- * LPD_ERR_TOO_LARGE (footprint above the whole budget, or a pivot row
- * longer than lp_solve_batch takes), LPD_ERR_NOT_FOUND
+ * LPD_ERR_TOO_LARGE (footprint above the whole budget), LPD_ERR_NOT_FOUND
  * (null or stopping server).  Thread-safe. */
 int64_t lpd_server_submit(lpd_server *server, int64_t m, int64_t n, const double *A, const double *b,
                           const double *c, double *x_out);

@@ -49,6 +49,7 @@ struct Request {
   double t_arrive = 0, t_admit = 0;
   uint64_t footprint = 0;
   bool has_ws = false;  // footprint includes a grid-walk workspace
+  bool wide = false;    // pivot row longer than the LDS: own grid launch each epoch
   // device side (resident requests)
   int32_t slot = -1;
   unsigned char* dmem = nullptr;  // inputs, x, then the workspace
@@ -232,25 +233,30 @@ void lpd_server::admit() {
 }
 
 void lpd_server::launch_epoch() {
-  const int32_t count = (int32_t)resident.size();
+  // LPs the batch kernel can place go into one batched launch; wide ones
+  // (pivot row longer than the LDS holds) each get a grid launch of their own
+  // after it, with column panels, resumable like the batch's team LPs.
+  std::vector<int32_t> in_batch, wide;
+  for (int32_t i = 0; i < (int32_t)resident.size(); ++i) (resident[(size_t)i].wide ? wide : in_batch).push_back(i);
+  const int32_t count = (int32_t)in_batch.size();
   std::vector<int64_t> m((size_t)count), n((size_t)count);
-  for (int32_t i = 0; i < count; ++i) {
-    m[(size_t)i] = resident[(size_t)i].m;
-    n[(size_t)i] = resident[(size_t)i].n;
+  for (int32_t j = 0; j < count; ++j) {
+    m[(size_t)j] = resident[(size_t)in_batch[(size_t)j]].m;
+    n[(size_t)j] = resident[(size_t)in_batch[(size_t)j]].n;
   }
-  BatchPlan P = plan_batch(count, m.data(), n.data(), knobs, nblocks, lds_limit);
-  hipError_t e = P.ok ? hipSuccess : hipErrorInvalidValue;
-  if (e == hipSuccess) {
-    const int maxb = batch_max_blocks(P.lds_bytes, P.condensed);
-    if (maxb <= 0) e = hipErrorInvalidValue;
-    else if (nblocks > maxb) P = plan_batch(count, m.data(), n.data(), knobs, maxb, lds_limit);
+  hipError_t e = hipSuccess;
+  BatchPlan P;
+  if (count > 0) {
+    P = plan_batch(count, m.data(), n.data(), knobs, nblocks, lds_limit);
+    if (!P.ok) e = hipErrorInvalidValue;
+    if (e == hipSuccess) {
+      const int maxb = batch_max_blocks(P.lds_bytes, P.condensed);
+      if (maxb <= 0) e = hipErrorInvalidValue;
+      else if (nblocks > maxb) P = plan_batch(count, m.data(), n.data(), knobs, maxb, lds_limit);
+    }
   }
-  std::vector<BatchItem> items((size_t)count);
-  for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
-    Request& r = resident[(size_t)i];
-    BatchItem& it = items[(size_t)i];
-    it = BatchItem{};
-    SolveArgs& a = it.a;
+  auto args_of = [&](const Request& r) {
+    SolveArgs a{};
     a.m = r.m;
     a.n = r.n;
     a.A = r.dA;
@@ -264,22 +270,30 @@ void lpd_server::launch_epoch() {
     a.status = d_status + r.slot;
     a.iterations = d_iter + r.slot;
     a.state = d_state + r.slot;
-    it.klass = P.klass[(size_t)i];
-    it.tclass = P.tclass[(size_t)i];
-    if (opt.pivots_per_epoch > 0) {
-      a.pivot_budget = opt.pivots_per_epoch;
-    } else {
-      // A pivot streams the tableau twice (read, write), split over the team.
-      const double team = it.klass == kClassTeam ? (double)P.cls_size[it.tclass] : 1.0;
-      const double k = (double)opt.epoch_bytes_per_wg * team / (2.0 * stored_bytes(r.m, r.n, knobs.condensed));
-      a.pivot_budget = (int64_t)std::max(1.0, std::min(k, 1e9));
-    }
+    return a;
+  };
+  // Pivots per epoch: a pivot streams the tableau twice (read, write), split
+  // over the workgroups the LP runs on.
+  auto budget_of = [&](const Request& r, double wgs) {
+    if (opt.pivots_per_epoch > 0) return (int64_t)opt.pivots_per_epoch;
+    const double k = (double)opt.epoch_bytes_per_wg * wgs / (2.0 * stored_bytes(r.m, r.n, knobs.condensed));
+    return (int64_t)std::max(1.0, std::min(k, 1e9));
+  };
+  std::vector<BatchItem> items((size_t)count);
+  for (int32_t j = 0; j < count && e == hipSuccess; ++j) {
+    const Request& r = resident[(size_t)in_batch[(size_t)j]];
+    BatchItem& it = items[(size_t)j];
+    it = BatchItem{};
+    it.a = args_of(r);
+    it.klass = P.klass[(size_t)j];
+    it.tclass = P.tclass[(size_t)j];
+    it.a.pivot_budget = budget_of(r, it.klass == kClassTeam ? (double)P.cls_size[it.tclass] : 1.0);
     it.ws = r.dws;
     // The planner's LDS test is the one submit used; never launch an LP
     // without the workspace its class walks over.
     if (it.klass != kClassLds && it.klass != kClassWave && !r.has_ws) e = hipErrorInvalidValue;
   }
-  if (e == hipSuccess && P.total > meta_bytes) {
+  if (e == hipSuccess && count > 0 && P.total > meta_bytes) {
     if (meta) (void)hipFreeAsync(meta, stream);
     meta = nullptr;
     meta_bytes = 0;
@@ -287,7 +301,19 @@ void lpd_server::launch_epoch() {
     if (e == hipSuccess) meta_bytes = P.total;
   }
   (void)hipEventRecord(ev_k0, stream);
-  if (e == hipSuccess) e = launch_batch(P, items, meta, stream);
+  if (e == hipSuccess && count > 0) e = launch_batch(P, items, meta, stream);
+  for (int32_t i : wide) {
+    if (e != hipSuccess) break;
+    const Request& r = resident[(size_t)i];
+    SolveArgs a = args_of(r);
+    const int nb = std::min(nblocks, grid_max_blocks(r.m, r.n, 0, knobs.condensed));
+    if (nb <= 0 || !r.has_ws) {
+      e = hipErrorInvalidValue;
+      break;
+    }
+    a.pivot_budget = budget_of(r, (double)nb);
+    e = launch_grid_solve(a, r.dws, nb, 0, stream, knobs.condensed);
+  }
   (void)hipEventRecord(ev_k1, stream);
   if (e != hipSuccess) (void)hipGetLastError();
   // Statuses, objectives and pivot counts of every slot in one copy each.
@@ -408,11 +434,13 @@ int64_t lpd_server_submit(lpd_server* s, int64_t m, int64_t n, const double* A, 
   if (m < 1 || n < 1) return LPD_ERR_INVALID_ARG;
   if (!A || !b || !c || !x_out) return LPD_ERR_NULL_POINTER;
   if (m > (1 << 30) || n > (1 << 30) || m + n + 1 > (1 << 30)) return LPD_ERR_SIZE_OVERFLOW;
-  // Same LDS tests as the batch planner: an LP it could not place would fail
-  // the whole epoch, so it is refused here.
-  if (!batch_can_place(m, n, s->knobs.condensed, s->lds_limit)) return LPD_ERR_TOO_LARGE;
-  const bool lds = wg_lds_bytes(m, n) + 256 <= s->lds_limit;
-  const uint64_t f = footprint_of(m, n, lds, s->knobs.condensed);
+  // Same LDS tests as the batch planner: an LP it cannot place runs as a
+  // grid launch of its own each epoch.
+  const bool wide = !batch_can_place(m, n, s->knobs.condensed, s->lds_limit);
+  const bool lds = !wide && wg_lds_bytes(m, n) + 256 <= s->lds_limit;
+  // A wide LP's workspace has barrier slots for a launch on every CU.
+  const uint64_t f = wide ? input_bytes(m, n) + grid_layout(m, n, s->nblocks, s->knobs.condensed).total
+                          : footprint_of(m, n, lds, s->knobs.condensed);
   if (f > s->budget) return LPD_ERR_TOO_LARGE;
   Request r;
   r.m = m;
@@ -423,6 +451,7 @@ int64_t lpd_server_submit(lpd_server* s, int64_t m, int64_t n, const double* A, 
   r.x_out = x_out;
   r.footprint = f;
   r.has_ws = !lds;
+  r.wide = wide;
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return LPD_ERR_NOT_FOUND;

@@ -126,10 +126,6 @@ def test_server_rejects_and_edge_cases():
         with pytest.raises(lpdense.LpdError) as e:
             tiny.submit(*lpgen.dense_lp(400, 500, 1))   # footprint above the whole budget
         assert e.value.code == -7
-    with lpdense.Server(1 << 32) as wide:
-        with pytest.raises(lpdense.LpdError) as e:
-            wide.submit(*lpgen.dense_lp(10, 25000, 1))  # pivot row longer than the LDS holds
-        assert e.value.code == -7
     with lpdense.Server(1 << 30, pivots_per_epoch=4, max_iter=7) as srv:
         ids = [srv.submit(*lp) for lp in lps]
         got = _drain(srv, len(ids))
@@ -161,3 +157,19 @@ def test_server_lp_moves_from_one_workgroup_to_a_team():
     for i, lp in zip(bids, bigs):
         _check_vs_oracle(lp, got[i])
     _check_vs_oracle(small, got[sid])
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["condensed", "full"])
+def test_server_wide_lps(full):
+    """LPs whose pivot row is longer than the LDS (10 x 25000, 6 x 40000)
+    run as grid launches of their own each epoch (column panels) beside the
+    batched ones; a budget of 3 pivots per epoch makes them suspend and
+    resume many times.  Every result equals the oracle's bits."""
+    lps = [lpgen.dense_lp(10, 25000, 2), lpgen.dense_lp(300, 200, 3), lpgen.dense_lp(6, 40000, 4),
+           lpgen.dense_lp(20, 30, 1), lpgen.dense_lp(700, 900, 5)]
+    announce(f"server with wide LPs full_tableau={full}")
+    with lpdense.Server(1 << 32, pivots_per_epoch=3, full_tableau=full) as srv:
+        ids = [srv.submit(*lp) for lp in lps]
+        got = _drain(srv, len(ids))
+    for i, lp in zip(ids, lps):
+        _check_vs_oracle(lp, got[i])
