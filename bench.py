@@ -338,9 +338,10 @@ def main():
     ap.add_argument("--workload", choices=["dense", "batch", "serve", "shapes"], default="dense")
     ap.add_argument("--generator", choices=["dense", "paper"], default="dense",
                     help="dense / shapes: the main generator, or the paper-style one (zeros in A, b = A x0)")
-    ap.add_argument("--schedule", choices=["auto", "condensed"], default="auto",
-                    help="dense: full tableau (auto: grid for large LPs) or the condensed tableau "
-                         "(nonbasic columns only, bitwise-identical results)")
+    ap.add_argument("--schedule", choices=["auto", "condensed", "paired"], default="auto",
+                    help="dense: full tableau (auto: grid for large LPs), the condensed tableau "
+                         "(nonbasic columns only) or two pivots per sweep of the full tableau; "
+                         "all give bitwise-identical results")
     ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates (LPs/s)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve: timed requests per rate")
     ap.add_argument("--serve-warmup", type=int, default=100, help="serve: untimed requests before them")
@@ -402,7 +403,8 @@ def main():
         del src, dst
         log("copied 1 GiB for counter calibration")
 
-    sched = lpdense.SCHED_GRID_CONDENSED if args.schedule == "condensed" else lpdense.SCHED_AUTO
+    sched = {"auto": lpdense.SCHED_AUTO, "condensed": lpdense.SCHED_GRID_CONDENSED,
+             "paired": lpdense.SCHED_GRID_PAIRED}[args.schedule]
 
     def step():
         return lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=sched,
@@ -432,12 +434,16 @@ def main():
     total_piv = sum(pivots)
     log(f"timed {args.steps} steps in {elapsed:.3f} s; pivots per step {pivots}; event ms {ev_ms}")
 
-    # Algorithmic bytes of one pivot: the stored tableau read and written once
-    # (the full tableau, or only the nonbasic columns and the RHS).
+    # Algorithmic bytes: the stored tableau read and written once per sweep
+    # (the full tableau, or only the nonbasic columns and the RHS).  A sweep
+    # does one pivot, or two on the paired schedule: ceil(pivots / 2) sweeps
+    # there, since a sweep takes one pivot only where the solve then ends.
     R, W = m + 1, (n + 1 if args.schedule == "condensed" else n + m + 1)
-    bytes_per_pivot = 16.0 * R * W
+    bytes_per_sweep = 16.0 * R * W
+    sweeps = [(p + 1) // 2 if args.schedule == "paired" else p for p in pivots]
+    bytes_per_pivot = bytes_per_sweep * sweeps[0] / max(pivots[0], 1)
     avg_ms = sum(ev_ms) / len(ev_ms)
-    achieved = bytes_per_pivot * (total_piv / args.steps) / (avg_ms / 1e3) / 1e9
+    achieved = bytes_per_sweep * (sum(sweeps) / args.steps) / (avg_ms / 1e3) / 1e9
     traffic = (counter_traffic(pivots[0]) if (m, n, args.seed) == (8192, 8192, 0) and args.schedule == "auto"
                and args.generator == "dense" else None)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -453,37 +459,43 @@ def main():
         it = int(r.iterations.item())
         if r.phase_ticks is not None and it > 2:
             t = r.phase_ticks.cpu().numpy()[1:it].astype(np.int64)
+            t = t[t[:, 0] > 0]  # paired schedule: one entry per sweep, at its first pivot
             d = np.median(np.diff(t[:, :7], axis=1), axis=0) * 10e-3  # us (100 MHz clock)
             tot = float(np.median(t[:, 6] - t[:, 0])) * 10e-3
-            phases = {"us_per_pivot_median": round(tot, 2), "pricing": round(d[0], 2),
+            phases = {"us_per_sweep_median": round(tot, 2), "pricing": round(d[0], 2),
                       "update_wg0": round(d[1], 2), "wait_last_wg": round(d[2], 2),
                       "release": round(d[3], 2), "detect": round(d[4], 2), "reduce": round(d[5], 2)}
             log(f"phases (median us/pivot): {phases}")
 
-    # Same LP on the condensed tableau (bitwise-identical results, fewer bytes
-    # per pivot): reported beside the full-tableau figures.
-    condensed = None
-    if args.schedule == "auto" and not args.no_condensed:
-        cd = lpdense.SCHED_GRID_CONDENSED
-        lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=cd, want_y=False, stream=stream)
+    # Same LP on the condensed tableau and with two pivots per sweep
+    # (bitwise-identical results, fewer bytes per pivot): reported beside the
+    # full-tableau figures.
+    def other_schedule(sc, bytes_per_sweep_sc, sweeps_of):
+        lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=sc, want_y=False, stream=stream)
         cs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         ce = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         rs = []
         for k in range(args.steps):
             cs[k].record(stream)
-            rs.append(lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=cd, want_y=False,
+            rs.append(lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=sc, want_y=False,
                                              stream=stream))
             ce[k].record(stream)
         torch.cuda.synchronize()
-        cms = sum(a.elapsed_time(b) for a, b in zip(cs, ce)) / args.steps
+        cms = sum(x.elapsed_time(y) for x, y in zip(cs, ce)) / args.steps
         cpiv = int(rs[0].iterations.item())
         same = all(bool(torch.equal(r.x.view(torch.int64), results[0].x.view(torch.int64))) for r in rs)
-        cbytes = 16.0 * (m + 1) * (n + 1)
-        condensed = {"pivots_per_s": round(cpiv / (cms / 1e3), 2), "ms_per_solve": round(cms, 3),
-                     "pivots_per_step": cpiv, "bytes_per_pivot": int(cbytes),
-                     "stored_bytes_GBps": round(cbytes * cpiv / (cms / 1e3) / 1e9, 1),
-                     "x_bitwise_equal_to_full_tableau": same}
+        return {"pivots_per_s": round(cpiv / (cms / 1e3), 2), "ms_per_solve": round(cms, 3),
+                "pivots_per_step": cpiv, "sweeps_per_step": sweeps_of(cpiv),
+                "bytes_per_sweep": int(bytes_per_sweep_sc),
+                "stored_bytes_GBps": round(bytes_per_sweep_sc * sweeps_of(cpiv) / (cms / 1e3) / 1e9, 1),
+                "x_bitwise_equal_to_full_tableau": same}
+
+    condensed = paired = None
+    if args.schedule == "auto" and not args.no_condensed:
+        condensed = other_schedule(lpdense.SCHED_GRID_CONDENSED, 16.0 * (m + 1) * (n + 1), lambda p: p)
         log(f"condensed tableau: {condensed}")
+        paired = other_schedule(lpdense.SCHED_GRID_PAIRED, 16.0 * (m + 1) * (n + m + 1), lambda p: (p + 1) // 2)
+        log(f"two pivots per sweep: {paired}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -506,13 +518,14 @@ def main():
         "config": {"workload": f"dense LP max c^T x, Ax<=b, x>=0, m={m}, n={n}, seed {args.seed}, "
                                + ("paper-style generator, " if args.generator == "paper" else "")
                                + "full solve from the slack basis (Dantzig, lowest-index ties)"
-                               + ("; condensed tableau (nonbasic columns only)" if args.schedule == "condensed"
-                                  else ""),
+                               + {"auto": "", "condensed": "; condensed tableau (nonbasic columns only)",
+                                  "paired": "; two pivots per sweep of the full tableau"}[args.schedule],
                    "schedule": args.schedule,
                    "m": m, "n": n, "pivots_per_step": pivots[0],
                    "status": lpdense.STATUS_NAMES[statuses[0]],
-                   "bytes_per_pivot": int(bytes_per_pivot),
-                   "max_iter": args.max_iter, "phases_us": phases, "condensed_tableau": condensed},
+                   "bytes_per_pivot": int(bytes_per_pivot), "sweeps_per_step": sweeps[0],
+                   "max_iter": args.max_iter, "phases_us": phases, "condensed_tableau": condensed,
+                   "two_pivots_per_sweep": paired},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -90,12 +90,18 @@ typedef enum lpd_schedule {
     LPD_SCHED_AUTO = 0,       /* library picks (workgroup if the tableau fits in LDS) */
     LPD_SCHED_WORKGROUP = 1,  /* one workgroup runs the whole pivot loop */
     LPD_SCHED_GRID = 2,       /* persistent cooperative grid, one grid barrier per pivot */
-    LPD_SCHED_GRID_CONDENSED = 3 /* the grid schedule on the condensed tableau: only the n
+    LPD_SCHED_GRID_CONDENSED = 3, /* the grid schedule on the condensed tableau: only the n
                                     columns of the nonbasic variables are stored and updated
                                     (the m basic columns of the full tableau are unit columns).
                                     Every output, the reconstructed full tableau included, is
                                     bitwise identical to the other schedules; a pivot moves
                                     16 (m+1)(n+1) bytes instead of 16 (m+1)(n+m+1) */
+    LPD_SCHED_GRID_PAIRED = 4 /* the grid schedule with two pivots per sweep of the full
+                                 tableau: the second pivot's entering column, ratio test and
+                                 normalised row are formed before the sweep, which then applies
+                                 both rank-1 updates to each element (the same roundings as two
+                                 sweeps: every output is bitwise identical to the other
+                                 schedules), moving about 8 (m+1)(n+m+1) bytes per pivot */
 } lpd_schedule;
 
 /*

@@ -85,7 +85,7 @@ int resolve_options(const lpd_problem* prob, const lpd_options* opt, SolveArgs* 
     if (opt->eps_d > 0) eps_d = opt->eps_d;
     if (opt->eps_p > 0) eps_p = opt->eps_p;
     if (opt->max_iter >= 0) max_iter = opt->max_iter;
-    if (opt->schedule < LPD_SCHED_AUTO || opt->schedule > LPD_SCHED_GRID_CONDENSED) return LPD_ERR_INVALID_ARG;
+    if (opt->schedule < LPD_SCHED_AUTO || opt->schedule > LPD_SCHED_GRID_PAIRED) return LPD_ERR_INVALID_ARG;
     if (opt->grid_blocks < 0) return LPD_ERR_INVALID_ARG;
     *schedule = opt->schedule;
     *grid_blocks = opt->grid_blocks;
@@ -245,11 +245,12 @@ int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd
     return hip_err(launch_wg_solve(a, stream));
 
   const bool condensed = schedule == LPD_SCHED_GRID_CONDENSED;
-  const int maxb = grid_max_blocks(a.m, a.n, 0, condensed);
+  const bool paired = schedule == LPD_SCHED_GRID_PAIRED;
+  const int maxb = grid_max_blocks(a.m, a.n, 0, condensed, paired);
   if (maxb <= 0) return LPD_ERR_TOO_LARGE;
   int nb = grid_blocks > 0 ? grid_blocks : dev.ncu;
   if (nb > maxb) nb = maxb;
-  const GridLayout L = grid_layout(a.m, a.n, nb, condensed);
+  const GridLayout L = grid_layout(a.m, a.n, nb, condensed, paired);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && L.total > total_b) return LPD_ERR_OUT_OF_MEMORY;
   void* ws = nullptr;
@@ -258,7 +259,7 @@ int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd
     (void)hipGetLastError();
     return hip_err(e);
   }
-  e = launch_grid_solve(a, ws, nb, 0, stream, condensed);
+  e = launch_grid_solve(a, ws, nb, 0, stream, condensed, paired);
   const hipError_t ef = hipFreeAsync(ws, stream);
   if (e != hipSuccess) return hip_err(e);
   return hip_err(ef);

@@ -8,12 +8,12 @@
 namespace lpd {
 namespace {
 
-template <int NT, int MAP, bool CD = false, bool PN = false>
+template <int NT, int MAP, bool CD = false, bool PN = false, bool FU = false>
 __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   uint32_t epoch = 0;
   const Team tm{(int)blockIdx.x, (int)gridDim.x, w.slots, &epoch};
-  team_solve<NT, MAP, CD, true, PN>(a, w, tm, smem);
+  team_solve<NT, MAP, CD, true, PN, FU>(a, w, tm, smem);
 }
 
 // Clears the barrier slots of a fresh workspace (stream-ordered, no memset node).
@@ -33,6 +33,8 @@ constexpr GridKernel kCondensed = grid_solve_kernel<kNT, 0, true>;
 // Pivot rows longer than the LDS holds: the sweep runs over column panels.
 constexpr GridKernel kPanelled = grid_solve_kernel<kNT, 0, false, true>;
 constexpr GridKernel kPanelledCondensed = grid_solve_kernel<kNT, 0, true, true>;
+// Two pivots per sweep (full tableau, two rows per column panel).
+constexpr GridKernel kPaired = grid_solve_kernel<kNT, 0, false, true, true>;
 
 // LPD_GRID_VARIANT (tuning / diagnostics) picks the thread mapping; 0 by default.
 int variant_index(int64_t) {
@@ -41,7 +43,8 @@ int variant_index(int64_t) {
   return (x >= 0 && x < kNumVariants) ? x : 0;
 }
 
-GridKernel pick_kernel(int64_t vw, bool condensed, bool panelled) {
+GridKernel pick_kernel(int64_t vw, bool condensed, bool panelled, bool paired = false) {
+  if (paired) return kPaired;
   if (panelled) return condensed ? kPanelledCondensed : kPanelled;
   return condensed ? kCondensed : kVariants[variant_index(vw)];
 }
@@ -59,13 +62,21 @@ int lds_limit() {
 // list is held one panel at a time: *vecs (the LDS row buffer, in vectors)
 // is then below vw, a multiple of 64, with room for a full capture list.
 // Returns 0 if even that does not fit.
-size_t lds_plan(int64_t m, int64_t n, int32_t* cap, int32_t* vecs, bool condensed) {
+size_t lds_plan(int64_t m, int64_t n, int32_t* cap, int32_t* vecs, bool condensed, bool paired = false) {
   const int64_t vw = grid_layout(m, n, 1, condensed).vw;
   const size_t limit = (size_t)lds_limit();
   const size_t fixed = kScratchBytes + 16;
   const size_t full_cap = (size_t)kCapMax * kCapEntryBytes;
   size_t c;
   int64_t v;
+  if (paired) {
+    // Two rows per panel: *vecs = 2 x the panel width (a multiple of 64).
+    if (limit < fixed + full_cap + 2 * 64 * 16) return 0;
+    const int64_t pw = std::min<int64_t>(round_up(vw, 64), (int64_t)((limit - fixed - full_cap) / 32) / 64 * 64);
+    *cap = kCapMax;
+    *vecs = (int32_t)(2 * pw);
+    return fixed + (size_t)(2 * pw) * 16 + full_cap;
+  }
   if (fixed + (size_t)vw * 16 + full_cap <= limit) {
     v = vw;
     c = kCapMax;
@@ -90,16 +101,16 @@ size_t grid_lds_bytes(int64_t m, int64_t n, int /*nthreads*/, bool condensed) {
   return lds_plan(m, n, &cap, &vecs, condensed);
 }
 
-int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed) {
+int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed, bool paired) {
   (void)nthreads;
   int32_t cap = 0, vecs = 0;
-  const size_t lds = lds_plan(m, n, &cap, &vecs, condensed);
+  const size_t lds = lds_plan(m, n, &cap, &vecs, condensed, paired);
   if (lds == 0) return 0;
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const int64_t vw = grid_layout(m, n, 1, condensed).vw;
-  auto fn = pick_kernel(vw, condensed, vecs < vw);
+  auto fn = pick_kernel(vw, condensed, vecs < vw, paired);
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0;
@@ -108,11 +119,13 @@ int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed) {
 }
 
 hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, int nthreads,
-                             hipStream_t stream, bool condensed) {
+                             hipStream_t stream, bool condensed, bool paired) {
   (void)nthreads;
-  const GridLayout L = grid_layout(a.m, a.n, nblocks, condensed);
+  // Two pivots per sweep: full tableau, not resumable.
+  if (paired && (condensed || a.state)) return hipErrorInvalidValue;
+  const GridLayout L = grid_layout(a.m, a.n, nblocks, condensed, paired);
   GridWork w = make_grid_work(L, a.m, workspace);
-  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap, &w.lds_vecs, condensed);
+  const size_t lds = lds_plan(a.m, a.n, &w.cap_cap, &w.lds_vecs, condensed, paired);
   if (lds == 0) return hipErrorInvalidValue;
 
   const int nslots = 2 * nblocks;
@@ -120,7 +133,7 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  auto fn = pick_kernel(L.vw, condensed, w.lds_vecs < L.vw);
+  auto fn = pick_kernel(L.vw, condensed, w.lds_vecs < L.vw, paired);
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   SolveArgs args = a;

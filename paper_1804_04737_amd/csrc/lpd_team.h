@@ -213,8 +213,16 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 // the sweep runs over column panels of w.lds_vecs vectors, panel after
 // panel, and a workgroup forms the panel of the normalised pivot row it
 // needs from the pivot row itself (same division as in P, so the same bits).
-template <int NT, int MAP, bool CD = false, bool DYN = true, bool PN = false>
+// FU = true (with PN, full tableau, not resumable) does two pivots per sweep
+// where it can: the P phase also prices the objective row after the first
+// pivot, forms the entering column of the second after the first update and
+// its ratio test, and the second normalised row; the sweep then applies both
+// updates to each element, fma(-a'_i, r2, fma(-f_i, r1, T)), the roundings of
+// two sweeps.  A pair takes one pivot where the second would not be made
+// (a status after the first, or the iteration cap).
+template <int NT, int MAP, bool CD = false, bool DYN = true, bool PN = false, bool FU = false>
 __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm, unsigned char* smem) {
+  static_assert(!FU || (PN && !CD), "two pivots per sweep: column panels, full tableau");
   Cand* scratch = reinterpret_cast<Cand*>(smem);
   dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
   // Capture list: elements of the entering column met during the sweep.
@@ -262,7 +270,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const int64_t chunk = (int64_t)kChunkSteps * NT;
   // Panels (PN): full panels of pvw vectors and a last one of pw_last; a
   // chunk never straddles two panels.
-  const int32_t pvw = PN ? w.lds_vecs : vw;
+  const int32_t pvw = PN ? (FU ? w.lds_vecs / 2 : w.lds_vecs) : vw;  // FU: two rows per panel
   const int32_t npan = PN ? (vw + pvw - 1) / pvw : 1;
   const int32_t pw_last = vw - (npan - 1) * pvw;
   const int64_t cpp = ((int64_t)m * pvw + chunk - 1) / chunk;  // chunks per full panel
@@ -396,7 +404,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   // ---------------- pivot loop ----------------
   const bool ticks = leader && a.phase_ticks != nullptr;
   int64_t done_here = 0;  // pivots done by this call
+  int64_t rnd = iter;     // sweeps done (FU: buffers alternate per sweep, not per pivot)
   while (status < 0) {
+    const int64_t rp = FU ? rnd : iter;  // parity of this sweep's buffers
     if (a.state && a.pivot_budget >= 0 && done_here == a.pivot_budget) break;  // suspend
     ++done_here;
     uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
@@ -406,9 +416,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     // them.
     if (dyn && leader && tid == 0)
       for (int h = 0; h < kTicketCounters; ++h)
-        __hip_atomic_store(w.tickets + h * kTicketStride + 32 * ((iter + 1) & 1), (uint32_t)h, __ATOMIC_RELAXED,
+        __hip_atomic_store(w.tickets + h * kTicketStride + 32 * ((rp + 1) & 1), (uint32_t)h, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    const int cur = (int)(iter & 1), nxt = cur ^ 1;
+    const int cur = (int)(rp & 1), nxt = cur ^ 1;
     double* obj_nxt = w.obj[nxt];
     const double* rhs_cur = own_sreg(w.rhs[cur]);
     double* rhs_nxt = own_sreg(w.rhs[nxt]);
@@ -458,43 +468,200 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       return on;
     };
     const dbl2* obj_cur = reinterpret_cast<const dbl2*>(w.obj[cur]);
-    for (int32_t v0 = tid; v0 < vw; v0 += 4 * NT) {
-      dbl2 t[4], o[4];
+    // Two pivots per sweep (FU): the pair's second pivot (k1, l1), its
+    // pivot p1, normalised right-hand side prhs1, the first update's
+    // multiplier of row l1 (fl1) and that row before the pair (rowl1).
+    bool two = false;
+    int32_t l1 = -1;
+    double p1 = 1.0, prhs1 = 0.0, fl1 = 0.0;
+    const dbl2* rowl1 = rowl;
+    dbl2* priv_rt = nullptr;
+    double* priv_ap = nullptr;
+    if constexpr (FU) {
+      priv_rt = reinterpret_cast<dbl2*>(w.priv + (int64_t)tm.rank * w.priv_stride);
+      priv_ap = w.priv + (int64_t)tm.rank * w.priv_stride + 2 * (int64_t)round_up(vw, 16);
+      // Pass 1: first pivot's normalised row (kept in this workgroup's private
+      // region) and the objective row after it, priced for k1.
+      Cand pc1 = cand_none();
+      for (int32_t v0 = tid; v0 < vw; v0 += 4 * NT) {
+        dbl2 t[4], o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int32_t v = v0 + q * NT;
-        if (v < vw) {
-          t[q] = gld2(rowl + v);
-          o[q] = gld2(obj_cur + v);
+        for (int q = 0; q < 4; ++q) {
+          const int32_t v = v0 + q * NT;
+          if (v < vw) {
+            t[q] = gld2(rowl + v);
+            o[q] = gld2(obj_cur + v);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int32_t v = v0 + q * NT;
+          if (v < vw) {
+            dbl2 r, on;
+            r.x = t[q].x / p;
+            r.y = t[q].y / p;
+            on.x = __builtin_fma(-g, r.x, o[q].x);
+            on.y = __builtin_fma(-g, r.y, o[q].y);
+            gst2(priv_rt + v, r);
+            price_offer(pc1, on.x, 2 * (int64_t)v, ncols);
+            price_offer(pc1, on.y, 2 * (int64_t)v + 1, ncols);
+          }
         }
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int32_t v = v0 + q * NT;
-        if (v < vw) (void)p_update(v, t[q], o[q]);
+      pc1 = block_reduce(pc1, scratch);  // also orders the private writes
+      const int32_t k1 = pc1.i;
+      const double g1 = pc1.v;
+      two = !(pc1.flags & kFlagNonFinite) && !(g1 >= -a.eps_d) && iter + 2 <= a.max_iter;
+      if (two) {
+        // Entering column k1 and right-hand side after the first pivot, and
+        // the second pivot's ratio test (Step 3), for every row.
+        const dbl2 rk = gld2(priv_rt + (k1 >> 1));
+        const double rt_k1 = (k1 & 1) ? rk.y : rk.x;
+        const double eps_p = a.eps_p;
+        Cand rc1 = cand_none();
+        for (int32_t i = tid; i < m; i += NT) {
+          double ap, rhp;
+          if (i == l) {
+            ap = rt_k1;
+            rhp = prhs;
+          } else {
+            const double f = gld(pcol_cur + i);
+            const double* rowi = (i == lprev) ? reinterpret_cast<const double*>(pr_prev) : Tm + (int64_t)i * ld;
+            ap = __builtin_fma(-f, rt_k1, gld(rowi + k1));
+            rhp = __builtin_fma(-f, prhs, gld(rhs_cur + i));
+          }
+          gst(priv_ap + i, ap);
+          ratio_offer(rc1, ap, rhp, i, eps_p);
+        }
+        rc1 = block_reduce(rc1, scratch);
+        if (rc1.i == kNoIndex || (rc1.flags & kFlagNonFinite)) {
+          two = false;
+        } else {
+          l1 = rc1.i;
+          p1 = rc1.aux;
+          fl1 = l1 == l ? 0.0 : gld(pcol_cur + l1);
+          const double rhp1 = l1 == l ? prhs : __builtin_fma(-fl1, prhs, gld(rhs_cur + l1));
+          prhs1 = rhp1 / p1;
+          rowl1 = (l1 == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(Tm + (int64_t)l1 * ld);
+        }
       }
-    }
-    if (leader && tid == 0) {
-      gst(rhs_nxt + m, __builtin_fma(-g, prhs, gld(rhs_cur + m)));
-      if constexpr (CD) {
-        if (lprev >= 0) w.basis[lprev] = kprev;  // the previous pivot's change, one pivot late
-        w.pos[vleave] = -1;
-        w.pos[k] = l;
-        w.lab[kc] = vleave;
-        w.col_of[vleave] = kc;
-        w.col_of[k] = -1;
+      if (two) {
+        // Pass 3: the second normalised row (row l1 after the first update,
+        // divided by p1) and the objective row after both pivots, priced for
+        // the next pair; this workgroup's slices of both are published.
+        const double g1c = g1;
+        Cand pc2 = cand_none();
+        for (int32_t v = tid; v < vw; v += NT) {
+          const dbl2 rt = gld2(priv_rt + v);
+          const dbl2 o = gld2(obj_cur + v);
+          dbl2 on, x, r1, on2;
+          on.x = __builtin_fma(-g, rt.x, o.x);
+          on.y = __builtin_fma(-g, rt.y, o.y);
+          if (l1 == l) {
+            x = rt;
+          } else {
+            const dbl2 t1 = gld2(rowl1 + v);
+            x.x = __builtin_fma(-fl1, rt.x, t1.x);
+            x.y = __builtin_fma(-fl1, rt.y, t1.y);
+          }
+          r1.x = x.x / p1;
+          r1.y = x.y / p1;
+          on2.x = __builtin_fma(-g1c, r1.x, on.x);
+          on2.y = __builtin_fma(-g1c, r1.y, on.y);
+          if (v >= pub_v0 && v < pub_v1) {
+            gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on2);
+            gst2(reinterpret_cast<dbl2*>(pr_cur) + v, r1);
+          }
+          price_offer(pc2, on2.x, 2 * (int64_t)v, ncols);
+          price_offer(pc2, on2.y, 2 * (int64_t)v + 1, ncols);
+        }
+        if (leader && tid == 0) {
+          const double z1 = __builtin_fma(-g, prhs, gld(rhs_cur + m));
+          gst(rhs_nxt + m, __builtin_fma(-g1c, prhs1, z1));
+          const int32_t leaving = w.basis[l];
+          w.pos[leaving] = -1;
+          w.pos[k] = l;
+          w.basis[l] = k;
+          const int32_t leaving1 = w.basis[l1];
+          w.pos[leaving1] = -1;
+          w.pos[k1] = l1;
+          w.basis[l1] = k1;
+          if (a.trace) {
+            if (iter < a.trace_cap) {
+              a.trace[2 * iter] = k;
+              a.trace[2 * iter + 1] = l;
+            }
+            if (iter + 1 < a.trace_cap) {
+              a.trace[2 * iter + 2] = k1;
+              a.trace[2 * iter + 3] = l1;
+            }
+          }
+        }
+        pc = block_reduce(pc2, scratch);
       } else {
-        const int32_t leaving = w.basis[l];
-        w.pos[leaving] = -1;
-        w.pos[k] = l;
-        w.basis[l] = k;
+        // One pivot this sweep: publish this workgroup's slices of the
+        // objective row after it and of its normalised row.
+        for (int32_t v = pub_v0 + tid; v < pub_v1; v += NT) {
+          const dbl2 rt = gld2(priv_rt + v);
+          const dbl2 o = gld2(obj_cur + v);
+          dbl2 on;
+          on.x = __builtin_fma(-g, rt.x, o.x);
+          on.y = __builtin_fma(-g, rt.y, o.y);
+          gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on);
+          gst2(reinterpret_cast<dbl2*>(pr_cur) + v, rt);
+        }
+        if (leader && tid == 0) {
+          gst(rhs_nxt + m, __builtin_fma(-g, prhs, gld(rhs_cur + m)));
+          const int32_t leaving = w.basis[l];
+          w.pos[leaving] = -1;
+          w.pos[k] = l;
+          w.basis[l] = k;
+          if (iter < a.trace_cap && a.trace) {
+            a.trace[2 * iter] = k;
+            a.trace[2 * iter + 1] = l;
+          }
+        }
+        pc = pc1;
       }
-      if (iter < a.trace_cap && a.trace) {
-        a.trace[2 * iter] = k;
-        a.trace[2 * iter + 1] = l;
+    } else {
+      for (int32_t v0 = tid; v0 < vw; v0 += 4 * NT) {
+        dbl2 t[4], o[4];
+  #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int32_t v = v0 + q * NT;
+          if (v < vw) {
+            t[q] = gld2(rowl + v);
+            o[q] = gld2(obj_cur + v);
+          }
+        }
+  #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int32_t v = v0 + q * NT;
+          if (v < vw) (void)p_update(v, t[q], o[q]);
+        }
       }
+      if (leader && tid == 0) {
+        gst(rhs_nxt + m, __builtin_fma(-g, prhs, gld(rhs_cur + m)));
+        if constexpr (CD) {
+          if (lprev >= 0) w.basis[lprev] = kprev;  // the previous pivot's change, one pivot late
+          w.pos[vleave] = -1;
+          w.pos[k] = l;
+          w.lab[kc] = vleave;
+          w.col_of[vleave] = kc;
+          w.col_of[k] = -1;
+        } else {
+          const int32_t leaving = w.basis[l];
+          w.pos[leaving] = -1;
+          w.pos[k] = l;
+          w.basis[l] = k;
+        }
+        if (iter < a.trace_cap && a.trace) {
+          a.trace[2 * iter] = k;
+          a.trace[2 * iter + 1] = l;
+        }
+      }
+      pc = block_reduce(pc, scratch);  // also orders the LDS writes of prow
     }
-    pc = block_reduce(pc, scratch);  // also orders the LDS writes of prow
     if (tk && tid == 0) tk[1] = __builtin_amdgcn_s_memrealtime();
     const int32_t kn = pc.i;                                  // entering variable of the next pivot
     const int32_t kcn = CD ? (int32_t)pc.aux : pc.i;          // ... and its stored column
@@ -534,9 +701,25 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           nv.x = __builtin_fma(-f, r.x, t.x);
           nv.y = __builtin_fma(-f, r.y, t.y);
         }
+        double ap = 0.0;  // FU: the second pivot's multiplier of row i
+        if constexpr (FU) {
+          if (two) {
+            ap = gld(priv_ap + i);
+            const dbl2 r2 = prow[pvw + v - pv0];
+            if (i == l1) {
+              nv = r2;
+            } else {
+              nv.x = __builtin_fma(-ap, r2.x, nv.x);
+              nv.y = __builtin_fma(-ap, r2.y, nv.y);
+            }
+          }
+        }
         if (cap) {
           const double an = kh ? nv.y : nv.x;
-          const double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
+          double rn = (i == l) ? prhs : __builtin_fma(-f, prhs, rh);
+          if constexpr (FU) {
+            if (two) rn = (i == l1) ? prhs1 : __builtin_fma(-ap, prhs1, rn);
+          }
           gst(pcol_nxt + i, an);
           gst(rhs_nxt + i, rn);
           const int32_t slot = cap_cap ? atomicAdd(cap_count, 1) : 0;
@@ -548,7 +731,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
             ratio_offer(rc, an, rn, i, eps_p);
           }
         }
-        if (i != l) st_stream(const_cast<dbl2*>(rowp) + v, nv);
+        // The pivot row of the sweep's last pivot is kept in pr_cur (written
+        // back by the next sweep).
+        if (i != (FU && two ? l1 : l)) st_stream(const_cast<dbl2*>(rowp) + v, nv);
       };
       // Ticket counters: counter h holds the next chunk it hands out and
       // steps by K (K = kTicketCounters): chunks h, h + K, h + 2K, ...  Each
@@ -561,7 +746,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       // one counter are ordered, a ticket past the end means every later
       // ticket of that counter is too.  (This pivot's counters were reset a
       // pivot ago.)
-      uint32_t* ctr0 = w.tickets + 32 * (iter & 1);
+      uint32_t* ctr0 = w.tickets + 32 * (rp & 1);
       const int home = tm.rank & (kTicketCounters - 1);
       uint32_t dry = 0;  // bit h: counter h has run dry (thread 0)
       auto request = [&]() -> uint32_t {
@@ -617,14 +802,33 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
             pv0 = pp * pvw;
             for (int32_t u = tid; u < pw; u += NT) {
               const int32_t vq = pv0 + u;
-              const dbl2 tr = gld2(rowl + vq);
               dbl2 r;
-              if constexpr (CD) {
-                r.x = 2 * vq == kc ? 1.0 / p : tr.x / p;
-                r.y = 2 * vq + 1 == kc ? 1.0 / p : tr.y / p;
+              if constexpr (FU) {
+                // Both normalised rows of the pair (as in P: same bits).
+                r = gld2(priv_rt + vq);
+                if (two) {
+                  dbl2 x;
+                  if (l1 == l) {
+                    x = r;
+                  } else {
+                    const dbl2 t1 = gld2(rowl1 + vq);
+                    x.x = __builtin_fma(-fl1, r.x, t1.x);
+                    x.y = __builtin_fma(-fl1, r.y, t1.y);
+                  }
+                  dbl2 r1;
+                  r1.x = x.x / p1;
+                  r1.y = x.y / p1;
+                  prow[pvw + u] = r1;
+                }
               } else {
-                r.x = tr.x / p;
-                r.y = tr.y / p;
+                const dbl2 tr = gld2(rowl + vq);
+                if constexpr (CD) {
+                  r.x = 2 * vq == kc ? 1.0 / p : tr.x / p;
+                  r.y = 2 * vq + 1 == kc ? 1.0 / p : tr.y / p;
+                } else {
+                  r.x = tr.x / p;
+                  r.y = tr.y / p;
+                }
               }
               prow[u] = r;
             }
@@ -749,10 +953,17 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     const Cand gr = grid_reduce(tm, rc, ++epoch, scratch, a.phase_ticks != nullptr, tk);
 
     // ---- loop control (identical decision in every workgroup)
-    ++iter;
-    lprev = l;
+    if constexpr (FU) {
+      iter += two ? 2 : 1;
+      lprev = two ? l1 : l;
+      ++rnd;
+      fpar = (int)(rnd & 1);
+    } else {
+      ++iter;
+      lprev = l;
+      fpar = (int)(iter & 1);
+    }
     kprev = k;
-    fpar = (int)(iter & 1);
     if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
     else if (pflags & kFlagNonFinite) status = kNumerical;
     else if (gn >= -a.eps_d) status = kOptimal;

@@ -18,7 +18,7 @@ OPTIMAL, UNBOUNDED, ITERATION_LIMIT, INFEASIBLE_START, NUMERICAL, DEVICE_TIMEOUT
 STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "NUMERICAL",
                 "DEVICE_TIMEOUT", "INFEASIBLE")
 ROW_LE, ROW_EQ, ROW_GE = 0, 1, 2
-SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED = 0, 1, 2, 3
+SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED, SCHED_GRID_PAIRED = 0, 1, 2, 3, 4
 
 # Exported symbols, as declared in include/lpdense.h.
 EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lp_solve_general", "lpd_server_create",

@@ -19,7 +19,7 @@ from tests.gpu_util import announce, assert_bitwise_equal, bits, gpu_solve
 
 pytestmark = pytest.mark.gpu
 
-GRID, CD = lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED
+GRID, CD, PAIR = lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED
 LDS_BYTES = 160 * 1024
 # Widest row that fits with a full capture list (scratch + 1024 entries of 20 B).
 ROW_VECS_MAX = (LDS_BYTES - 32 * 24 - 16 - 1024 * 20) // 16
@@ -33,6 +33,7 @@ def stored_vecs(m, n, schedule):
     (64, 20000, 0, GRID), (64, 20000, 2, GRID), (64, 20000, 7, GRID),
     (40, 45000, 0, GRID), (40, 45000, 3, GRID), (24, 80000, 2, GRID),
     (64, 20000, 0, CD), (64, 20000, 2, CD), (40, 45000, 3, CD),
+    (64, 20000, 0, PAIR), (64, 20000, 2, PAIR), (24, 80000, 2, PAIR),
 ], ids=lambda v: str(v))
 def test_panelled_rows_bitwise(m, n, blocks, schedule):
     assert stored_vecs(m, n, schedule) > ROW_VECS_MAX  # the panelled kernel runs
