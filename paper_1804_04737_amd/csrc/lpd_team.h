@@ -51,6 +51,7 @@ constexpr int kCapMax = 1024;     // LDS capture-list entries (entering-column e
 constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
 constexpr int kChunkSteps = 2;                 // dynamic sweep chunk: 2 x NT vectors
+constexpr int kChunkStepsPaired = 3;           // ... with two pivots per sweep
 constexpr int64_t kStaticSteps = 16;           // static grid steps before the dynamic part
 constexpr int64_t kDynMinSteps = 48;           // sweeps shorter than this are all static
 
@@ -267,7 +268,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   // the last chunk's latency); it only pays off on long sweeps.
   const bool dyn = DYN && nb > 1 && steps_total >= kDynMinSteps;
   const int64_t e_static = dyn ? min((int64_t)kStaticSteps * G, e_total) : e_total;
-  const int64_t chunk = (int64_t)kChunkSteps * NT;
+  // Two pivots per sweep do twice the work per element: longer chunks there.
+  constexpr int kCS = FU ? kChunkStepsPaired : kChunkSteps;
+  const int64_t chunk = (int64_t)kCS * NT;
   // Panels (PN): full panels of pvw vectors and a last one of pw_last; a
   // chunk never straddles two panels.
   const int32_t pvw = PN ? (FU ? w.lds_vecs / 2 : w.lds_vecs) : vw;  // FU: two rows per panel
@@ -680,9 +683,23 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       // One element (i, v) of the dynamic part: the same work as one step of
       // the static walk below.
       int32_t pv0 = 0;  // first vector of the panel in LDS (PN)
+      // FU: the row multipliers of the pair (f_i, a'_i) are kept from this
+      // thread's previous element while the row stays the same.
+      int32_t ci = -1;
+      double cf = 0.0, cap2 = 0.0;
       auto element = [&](int32_t i, int32_t v) {
         const dbl2* rowp = reinterpret_cast<const dbl2*>(Tm) + (int64_t)i * ldv;
-        const double f = gld(pcol_cur + i);
+        double f;
+        if constexpr (FU) {
+          if (i != ci) {
+            ci = i;
+            cf = gld(pcol_cur + i);
+            if (two) cap2 = gld(priv_ap + i);
+          }
+          f = cf;
+        } else {
+          f = gld(pcol_cur + i);
+        }
         const bool cap = (v == kv);
         double rh = 0.0;
         if (cap) rh = gld(rhs_cur + i);
@@ -704,7 +721,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         double ap = 0.0;  // FU: the second pivot's multiplier of row i
         if constexpr (FU) {
           if (two) {
-            ap = gld(priv_ap + i);
+            ap = cap2;
             const dbl2 r2 = prow[pvw + v - pv0];
             if (i == l1) {
               nv = r2;
@@ -776,9 +793,18 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
               while (dry != kAllDry) {
                 const uint32_t t = tq0;
                 tq0 = tq1;
-                if (t < n_chunks) {
-                  cn = t;
-                  break;
+                {
+                  // Counter h hands out a contiguous share of the chunks
+                  // (ticket j: chunk h * per + j), so the workgroups of
+                  // different counters work in different panels and do
+                  // not all change panels at once.
+                  const uint32_t h = t % (uint32_t)kTicketCounters, j = t / (uint32_t)kTicketCounters;
+                  const uint32_t per = (n_chunks + kTicketCounters - 1) / kTicketCounters;
+                  const uint32_t lo = h * per, hi = min(n_chunks, lo + per);
+                  if (lo + j < hi) {
+                    cn = lo + j;
+                    break;
+                  }
                 }
                 dry |= 1u << (t % (uint32_t)kTicketCounters);
                 if (dry != kAllDry) tq1 = request();
@@ -838,7 +864,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           const int64_t e0 = lc * chunk + tid;
           int32_t ii = (int32_t)(e0 / pw), vv = (int32_t)(e0 % pw);
           const int32_t pq = NT / pw, pr = NT % pw;
-          for (int qq = 0; qq < kChunkSteps; ++qq) {
+          for (int qq = 0; qq < kCS; ++qq) {
             if (ii < m) element(ii, pv0 + vv);
             if (dyn && qq == 0 && tid == 0) tq1 = request();
             vv += pr;
