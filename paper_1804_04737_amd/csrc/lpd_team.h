@@ -52,6 +52,7 @@ constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
 constexpr int kChunkSteps = 2;                 // dynamic sweep chunk: 2 x NT vectors
 constexpr int kChunkStepsPaired = 3;           // ... with two pivots per sweep
+constexpr int kReadDoneWord = 64;              // ticket region word of the paired sweep's read-done count
 constexpr int64_t kStaticSteps = 16;           // static grid steps before the dynamic part
 constexpr int64_t kDynMinSteps = 48;           // sweeps shorter than this are all static
 
@@ -356,6 +357,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         __hip_atomic_store(w.tickets + h * kTicketStride + 32, (uint32_t)h, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
+      if (FU) __hip_atomic_store(w.tickets + kReadDoneWord, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     {
       Cand f0 = cand_none();
@@ -548,6 +550,12 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           rowl1 = (l1 == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(Tm + (int64_t)l1 * ld);
         }
       }
+      // This round's reads of tableau cells that its sweep rewrites (row l in
+      // pass 1, column k1 in the gather) have returned in every wave (their
+      // values were consumed before the last block reduction): count this
+      // workgroup in.  No workgroup's sweep starts before all have.
+      if (tid == 0 && nb > 1)
+        __hip_atomic_fetch_add(w.tickets + kReadDoneWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (two) {
         // Pass 3: the second normalised row (row l1 after the first update,
         // divided by p1) and the objective row after both pivots, priced for
@@ -673,6 +681,25 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
 
     // ---- Q_t: Step 5 on every constraint row, fused with Step 3 for k_{t+1}.
     Cand rc = cand_none();
+    if constexpr (FU) {
+      // Wait until every workgroup has read this round's cells of row l and
+      // column k1 (see the P phase); a bounded wait like the barrier's.
+      if (nb > 1) {
+        if (tid == 0) {
+          const uint32_t target = (uint32_t)nb * (uint32_t)(rnd + 1);
+          const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+          while ((int32_t)(__hip_atomic_load(w.tickets + kReadDoneWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                           target) < 0) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__builtin_amdgcn_s_memrealtime() - t0 > kWatchdogTicks) {
+              rc.flags |= kFlagTimeout;
+              break;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
     {
       const int32_t kv = kcn >> 1, kh = kcn & 1;
       // Condensed: stored column kc becomes the leaving variable's column,
