@@ -465,6 +465,10 @@ def main():
             phases = {"us_per_sweep_median": round(tot, 2), "pricing": round(d[0], 2),
                       "update_wg0": round(d[1], 2), "wait_last_wg": round(d[2], 2),
                       "release": round(d[3], 2), "detect": round(d[4], 2), "reduce": round(d[5], 2)}
+            if args.schedule == "paired":
+                # Entry 7: end of the wait at the pair's publication barrier
+                # (part of the update share above).
+                phases["pair_barrier_wait"] = round(float(np.median(t[:, 7] - t[:, 1])) * 10e-3, 2)
             log(f"phases (median us/pivot): {phases}")
 
     # Same LP on the condensed tableau and with two pivots per sweep

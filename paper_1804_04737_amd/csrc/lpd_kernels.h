@@ -79,10 +79,13 @@ struct GridWork {
   int32_t* col_of; // n+m: stored column of each nonbasic variable, -1 if basic
   uint32_t* tickets;   // sweep chunk tickets: counter h of pivot parity q at [h * kTicketStride + 32 q]
   BarrierSlot* slots; // 2 * nblocks
-  // Two pivots per sweep only: a private region per workgroup (priv_stride
-  // doubles each): the normalised pivot row of the pair's first pivot (2 vw
-  // doubles), then the entering column of its second pivot after the first
-  // update (m doubles).
+  // Two pivots per sweep only: the normalised pivot row of the pair's first
+  // pivot (ld doubles) and the entering column of its second pivot after the
+  // first update (m doubles), each workgroup writing one slice of each; and a
+  // private copy of that row per workgroup (priv_stride doubles each), used
+  // where the row is longer than the LDS.
+  double* prt;
+  double* pap;
   double* priv;
   int64_t priv_stride;
   int32_t cap_cap;     // capacity of the LDS capture list (entries)
@@ -93,8 +96,7 @@ struct GridWork {
 struct GridLayout {
   int64_t ld, vw;
   uint64_t off_T, off_obj, off_pr, off_pcol, off_rhs, off_basis, off_pos, off_lab, off_colof, off_tickets,
-      off_priv, off_slots, total;
-  int64_t priv_stride;  // doubles per workgroup (paired only)
+      off_pair, off_priv, off_slots, total;
 };
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
@@ -102,7 +104,8 @@ __host__ __device__ inline int64_t round_up(int64_t x, int64_t q) { return (x + 
 // Workspace of one team solve of an m x n LP by `nblocks` workgroups.  The
 // full tableau stores the n+m columns of Table 1; the condensed one only the
 // n columns of the nonbasic variables (the basic ones are unit columns).
-// `paired` (two pivots per sweep) adds a private region per workgroup.
+// `paired` (two pivots per sweep) adds one row and one column, and one row
+// per workgroup.
 __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblocks, bool condensed = false,
                                                  bool paired = false) {
   GridLayout L{};
@@ -124,8 +127,8 @@ __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int nblo
   L.off_lab = take(condensed ? (uint64_t)(n + 1) * 4 : 0);  // n + 1: read in pairs
   L.off_colof = take(condensed ? (uint64_t)(n + m) * 4 : 0);
   L.off_tickets = take((uint64_t)kTicketCounters * kTicketStride * 4);  // one 4 KiB block per counter
-  L.priv_stride = paired ? round_up(2 * L.vw, 32) + round_up(m, 32) : 0;
-  L.off_priv = take((uint64_t)nblocks * (uint64_t)L.priv_stride * 8);
+  L.off_pair = take(paired ? (uint64_t)(L.ld + round_up(m, 32)) * 8 : 0);
+  L.off_priv = take(paired ? (uint64_t)nblocks * (uint64_t)L.ld * 8 : 0);
   L.off_slots = take(2ull * nblocks * sizeof(BarrierSlot));
   L.total = off;
   return L;
@@ -149,8 +152,10 @@ __host__ __device__ inline GridWork make_grid_work(const GridLayout& L, int64_t 
   w.lab = reinterpret_cast<int32_t*>(base + L.off_lab);
   w.col_of = reinterpret_cast<int32_t*>(base + L.off_colof);
   w.tickets = reinterpret_cast<uint32_t*>(base + L.off_tickets);
+  w.prt = reinterpret_cast<double*>(base + L.off_pair);
+  w.pap = w.prt + L.ld;
   w.priv = reinterpret_cast<double*>(base + L.off_priv);
-  w.priv_stride = L.priv_stride;
+  w.priv_stride = L.ld;
   w.slots = reinterpret_cast<BarrierSlot*>(base + L.off_slots);
   return w;
 }

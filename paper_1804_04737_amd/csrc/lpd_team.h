@@ -221,7 +221,10 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 // its ratio test, and the second normalised row; the sweep then applies both
 // updates to each element, fma(-a'_i, r2, fma(-f_i, r1, T)), the roundings of
 // two sweeps.  A pair takes one pivot where the second would not be made
-// (a status after the first, or the iteration cap).
+// (a status after the first, or the iteration cap).  Each workgroup publishes
+// a slice of the first normalised row and of the second multiplier column;
+// a counter barrier after the column gather makes them visible before any
+// sweep starts (the sweep also rewrites row l and column k1, which P reads).
 template <int NT, int MAP, bool CD = false, bool DYN = true, bool PN = false, bool FU = false>
 __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm, unsigned char* smem) {
   static_assert(!FU || (PN && !CD), "two pivots per sweep: column panels, full tableau");
@@ -272,10 +275,13 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   // Two pivots per sweep do twice the work per element: longer chunks there.
   constexpr int kCS = FU ? kChunkStepsPaired : kChunkSteps;
   const int64_t chunk = (int64_t)kCS * NT;
-  // Panels (PN): full panels of pvw vectors and a last one of pw_last; a
-  // chunk never straddles two panels.
-  const int32_t pvw = PN ? (FU ? w.lds_vecs / 2 : w.lds_vecs) : vw;  // FU: two rows per panel
-  const int32_t npan = PN ? (vw + pvw - 1) / pvw : 1;
+  // Panels (PN): as few as the LDS allows, of nearly equal width in whole
+  // 128-byte lines (npan - 1 panels of pvw vectors and a last one of
+  // pw_last; unequal panels leave one ticket counter's workgroups changing
+  // panels at the end of the sweep); a chunk never straddles two panels.
+  const int32_t pvw_max = PN ? (FU ? w.lds_vecs / 2 : w.lds_vecs) : vw;  // FU: two rows per panel
+  const int32_t npan = PN ? (vw + pvw_max - 1) / pvw_max : 1;
+  const int32_t pvw = PN ? min(pvw_max, (int32_t)round_up((vw + npan - 1) / npan, 8)) : vw;
   const int32_t pw_last = vw - (npan - 1) * pvw;
   const int64_t cpp = ((int64_t)m * pvw + chunk - 1) / chunk;  // chunks per full panel
   const uint32_t n_chunks =
@@ -480,13 +486,21 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     int32_t l1 = -1;
     double p1 = 1.0, prhs1 = 0.0, fl1 = 0.0;
     const dbl2* rowl1 = rowl;
-    dbl2* priv_rt = nullptr;
-    double* priv_ap = nullptr;
+    dbl2* const prt = FU ? own_sreg(reinterpret_cast<dbl2*>(w.prt)) : nullptr;
+    double* const pap = FU ? own_sreg(w.pap) : nullptr;
+    // FU: this workgroup's own copy of r_t for its later passes, in LDS when
+    // the row fits (the sweep's first panel load overwrites it), else in its
+    // private region.
+    const bool rt_lds = vw <= w.lds_vecs;
+    dbl2* const priv_rt = FU ? reinterpret_cast<dbl2*>(w.priv + (int64_t)tm.rank * w.priv_stride) : nullptr;
+    auto keep_rt = [&](int32_t v, dbl2 r) {
+      if (rt_lds) prow[v] = r;
+      else gst2(priv_rt + v, r);
+    };
+    auto kept_rt = [&](int32_t v) -> dbl2 { return rt_lds ? prow[v] : gld2(priv_rt + v); };
     if constexpr (FU) {
-      priv_rt = reinterpret_cast<dbl2*>(w.priv + (int64_t)tm.rank * w.priv_stride);
-      priv_ap = w.priv + (int64_t)tm.rank * w.priv_stride + 2 * (int64_t)round_up(vw, 16);
-      // Pass 1: first pivot's normalised row (kept in this workgroup's private
-      // region) and the objective row after it, priced for k1.
+      // Pass 1: first pivot's normalised row (kept, and this workgroup's
+      // slice published) and the objective row after it, priced for k1.
       Cand pc1 = cand_none();
       for (int32_t v0 = tid; v0 < vw; v0 += 4 * NT) {
         dbl2 t[4], o[4];
@@ -507,21 +521,24 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
             r.y = t[q].y / p;
             on.x = __builtin_fma(-g, r.x, o[q].x);
             on.y = __builtin_fma(-g, r.y, o[q].y);
-            gst2(priv_rt + v, r);
+            keep_rt(v, r);
+            if (v >= pub_v0 && v < pub_v1) gst2(prt + v, r);
             price_offer(pc1, on.x, 2 * (int64_t)v, ncols);
             price_offer(pc1, on.y, 2 * (int64_t)v + 1, ncols);
           }
         }
       }
-      pc1 = block_reduce(pc1, scratch);  // also orders the private writes
+      pc1 = block_reduce(pc1, scratch);  // also orders the kept row's writes
       const int32_t k1 = pc1.i;
       const double g1 = pc1.v;
       two = !(pc1.flags & kFlagNonFinite) && !(g1 >= -a.eps_d) && iter + 2 <= a.max_iter;
       if (two) {
         // Entering column k1 and right-hand side after the first pivot, and
         // the second pivot's ratio test (Step 3), for every row.
-        const dbl2 rk = gld2(priv_rt + (k1 >> 1));
+        const dbl2 rk = kept_rt(k1 >> 1);
         const double rt_k1 = (k1 & 1) ? rk.y : rk.x;
+        // This workgroup publishes rows [pa0, pa1) of the column.
+        const int32_t pa0 = (int32_t)((int64_t)m * tm.rank / nb), pa1 = (int32_t)((int64_t)m * (tm.rank + 1) / nb);
         const double eps_p = a.eps_p;
         Cand rc1 = cand_none();
         for (int32_t i = tid; i < m; i += NT) {
@@ -535,7 +552,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
             ap = __builtin_fma(-f, rt_k1, gld(rowi + k1));
             rhp = __builtin_fma(-f, prhs, gld(rhs_cur + i));
           }
-          gst(priv_ap + i, ap);
+          if (i >= pa0 && i < pa1) gst(pap + i, ap);
           ratio_offer(rc1, ap, rhp, i, eps_p);
         }
         rc1 = block_reduce(rc1, scratch);
@@ -550,12 +567,19 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           rowl1 = (l1 == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(Tm + (int64_t)l1 * ld);
         }
       }
-      // This round's reads of tableau cells that its sweep rewrites (row l in
-      // pass 1, column k1 in the gather) have returned in every wave (their
-      // values were consumed before the last block reduction): count this
-      // workgroup in.  No workgroup's sweep starts before all have.
-      if (tid == 0 && nb > 1)
-        __hip_atomic_fetch_add(w.tickets + kReadDoneWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // Arrival at the pair's publication barrier: this workgroup's slices of
+      // r_t and of the column after the first pivot are written back, and
+      // its reads of row l and column k1, which the sweep rewrites, have
+      // returned.  No sweep starts before every workgroup has arrived; the
+      // third pass below overlaps the wait.
+      if (nb > 1) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_fetch_add(w.tickets + kReadDoneWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
       if (two) {
         // Pass 3: the second normalised row (row l1 after the first update,
         // divided by p1) and the objective row after both pivots, priced for
@@ -563,7 +587,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         const double g1c = g1;
         Cand pc2 = cand_none();
         for (int32_t v = tid; v < vw; v += NT) {
-          const dbl2 rt = gld2(priv_rt + v);
+          const dbl2 rt = kept_rt(v);
           const dbl2 o = gld2(obj_cur + v);
           dbl2 on, x, r1, on2;
           on.x = __builtin_fma(-g, rt.x, o.x);
@@ -613,7 +637,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         // One pivot this sweep: publish this workgroup's slices of the
         // objective row after it and of its normalised row.
         for (int32_t v = pub_v0 + tid; v < pub_v1; v += NT) {
-          const dbl2 rt = gld2(priv_rt + v);
+          const dbl2 rt = kept_rt(v);
           const dbl2 o = gld2(obj_cur + v);
           dbl2 on;
           on.x = __builtin_fma(-g, rt.x, o.x);
@@ -682,8 +706,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     // ---- Q_t: Step 5 on every constraint row, fused with Step 3 for k_{t+1}.
     Cand rc = cand_none();
     if constexpr (FU) {
-      // Wait until every workgroup has read this round's cells of row l and
-      // column k1 (see the P phase); a bounded wait like the barrier's.
+      // Wait until every workgroup has arrived (after its column gather),
+      // then acquire their slices; a bounded wait like the barrier's.
       if (nb > 1) {
         if (tid == 0) {
           const uint32_t target = (uint32_t)nb * (uint32_t)(rnd + 1);
@@ -696,9 +720,14 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
               break;
             }
           }
+          // One acquire per workgroup: it invalidates the XCD's L2 and this
+          // CU's L1, which the other waves share after the barrier.  (An
+          // acquire in every wave costs the sweep ~25 us at 8192 x 8192.)
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
       }
+      if (tk && tid == 0) tk[7] = __builtin_amdgcn_s_memrealtime();
     }
     {
       const int32_t kv = kcn >> 1, kh = kcn & 1;
@@ -721,7 +750,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           if (i != ci) {
             ci = i;
             cf = gld(pcol_cur + i);
-            if (two) cap2 = gld(priv_ap + i);
+            if (two) cap2 = gld(pap + i);
           }
           f = cf;
         } else {
@@ -810,6 +839,14 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         // panel's m x pw block in row-major order.  Chunks come from the
         // tickets on long sweeps, else in the static order rank, rank + nb, ...
         constexpr uint32_t kAllDry = (1u << kTicketCounters) - 1u;
+        // First chunk of counter h's share: whole panels when the panels
+        // divide evenly between the counters, else an even split.
+        auto share_lo = [&](uint32_t h) -> uint32_t {
+          if (h >= (uint32_t)kTicketCounters) return n_chunks;
+          if (npan % kTicketCounters == 0) return (uint32_t)((int64_t)h * (npan / kTicketCounters) * cpp);
+          const uint32_t per = (n_chunks + kTicketCounters - 1) / kTicketCounters;
+          return min(n_chunks, h * per);
+        };
         int32_t loaded = -1;
         uint32_t jst = 0;
         for (int par = 0;; par ^= 1) {
@@ -826,8 +863,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
                   // different counters work in different panels and do
                   // not all change panels at once.
                   const uint32_t h = t % (uint32_t)kTicketCounters, j = t / (uint32_t)kTicketCounters;
-                  const uint32_t per = (n_chunks + kTicketCounters - 1) / kTicketCounters;
-                  const uint32_t lo = h * per, hi = min(n_chunks, lo + per);
+                  const uint32_t lo = share_lo(h), hi = share_lo(h + 1);
                   if (lo + j < hi) {
                     cn = lo + j;
                     break;
@@ -857,8 +893,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
               const int32_t vq = pv0 + u;
               dbl2 r;
               if constexpr (FU) {
-                // Both normalised rows of the pair (as in P: same bits).
-                r = gld2(priv_rt + vq);
+                // Both normalised rows of the pair (as in P: same bits); r_t
+                // as the workgroups published it.  Row l1 is not rewritten
+                // by this sweep.
+                r = gld2(prt + vq);
                 if (two) {
                   dbl2 x;
                   if (l1 == l) {
