@@ -338,7 +338,7 @@ def main():
     ap.add_argument("--workload", choices=["dense", "batch", "serve", "shapes"], default="dense")
     ap.add_argument("--generator", choices=["dense", "paper"], default="dense",
                     help="dense / shapes: the main generator, or the paper-style one (zeros in A, b = A x0)")
-    ap.add_argument("--schedule", choices=["auto", "condensed", "paired"], default="auto",
+    ap.add_argument("--schedule", choices=["auto", "condensed", "paired", "condensed_paired"], default="auto",
                     help="dense: full tableau (auto: grid for large LPs), the condensed tableau "
                          "(nonbasic columns only) or two pivots per sweep of the full tableau; "
                          "all give bitwise-identical results")
@@ -404,7 +404,8 @@ def main():
         log("copied 1 GiB for counter calibration")
 
     sched = {"auto": lpdense.SCHED_AUTO, "condensed": lpdense.SCHED_GRID_CONDENSED,
-             "paired": lpdense.SCHED_GRID_PAIRED}[args.schedule]
+             "paired": lpdense.SCHED_GRID_PAIRED,
+             "condensed_paired": lpdense.SCHED_GRID_CONDENSED_PAIRED}[args.schedule]
 
     def step():
         return lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=sched,
@@ -438,9 +439,9 @@ def main():
     # (the full tableau, or only the nonbasic columns and the RHS).  A sweep
     # does one pivot, or two on the paired schedule: ceil(pivots / 2) sweeps
     # there, since a sweep takes one pivot only where the solve then ends.
-    R, W = m + 1, (n + 1 if args.schedule == "condensed" else n + m + 1)
+    R, W = m + 1, (n + 1 if args.schedule in ("condensed", "condensed_paired") else n + m + 1)
     bytes_per_sweep = 16.0 * R * W
-    sweeps = [(p + 1) // 2 if args.schedule == "paired" else p for p in pivots]
+    sweeps = [(p + 1) // 2 if args.schedule in ("paired", "condensed_paired") else p for p in pivots]
     bytes_per_pivot = bytes_per_sweep * sweeps[0] / max(pivots[0], 1)
     avg_ms = sum(ev_ms) / len(ev_ms)
     achieved = bytes_per_sweep * (sum(sweeps) / args.steps) / (avg_ms / 1e3) / 1e9
@@ -465,7 +466,7 @@ def main():
             phases = {"us_per_sweep_median": round(tot, 2), "pricing": round(d[0], 2),
                       "update_wg0": round(d[1], 2), "wait_last_wg": round(d[2], 2),
                       "release": round(d[3], 2), "detect": round(d[4], 2), "reduce": round(d[5], 2)}
-            if args.schedule == "paired":
+            if args.schedule in ("paired", "condensed_paired"):
                 # Entry 7: end of the wait at the pair's publication barrier
                 # (part of the update share above).
                 phases["pair_barrier_wait"] = round(float(np.median(t[:, 7] - t[:, 1])) * 10e-3, 2)
@@ -494,12 +495,15 @@ def main():
                 "stored_bytes_GBps": round(bytes_per_sweep_sc * sweeps_of(cpiv) / (cms / 1e3) / 1e9, 1),
                 "x_bitwise_equal_to_full_tableau": same}
 
-    condensed = paired = None
+    condensed = paired = condensed_paired = None
     if args.schedule == "auto" and not args.no_condensed:
         condensed = other_schedule(lpdense.SCHED_GRID_CONDENSED, 16.0 * (m + 1) * (n + 1), lambda p: p)
         log(f"condensed tableau: {condensed}")
         paired = other_schedule(lpdense.SCHED_GRID_PAIRED, 16.0 * (m + 1) * (n + m + 1), lambda p: (p + 1) // 2)
         log(f"two pivots per sweep: {paired}")
+        condensed_paired = other_schedule(lpdense.SCHED_GRID_CONDENSED_PAIRED, 16.0 * (m + 1) * (n + 1),
+                                          lambda p: (p + 1) // 2)
+        log(f"two pivots per sweep of the condensed tableau: {condensed_paired}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -523,13 +527,14 @@ def main():
                                + ("paper-style generator, " if args.generator == "paper" else "")
                                + "full solve from the slack basis (Dantzig, lowest-index ties)"
                                + {"auto": "", "condensed": "; condensed tableau (nonbasic columns only)",
-                                  "paired": "; two pivots per sweep of the full tableau"}[args.schedule],
+                                  "paired": "; two pivots per sweep of the full tableau",
+                                  "condensed_paired": "; two pivots per sweep of the condensed tableau"}[args.schedule],
                    "schedule": args.schedule,
                    "m": m, "n": n, "pivots_per_step": pivots[0],
                    "status": lpdense.STATUS_NAMES[statuses[0]],
                    "bytes_per_pivot": int(bytes_per_pivot), "sweeps_per_step": sweeps[0],
                    "max_iter": args.max_iter, "phases_us": phases, "condensed_tableau": condensed,
-                   "two_pivots_per_sweep": paired},
+                   "two_pivots_per_sweep": paired, "condensed_two_pivots_per_sweep": condensed_paired},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

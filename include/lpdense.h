@@ -96,12 +96,15 @@ typedef enum lpd_schedule {
                                     Every output, the reconstructed full tableau included, is
                                     bitwise identical to the other schedules; a pivot moves
                                     16 (m+1)(n+1) bytes instead of 16 (m+1)(n+m+1) */
-    LPD_SCHED_GRID_PAIRED = 4 /* the grid schedule with two pivots per sweep of the full
+    LPD_SCHED_GRID_PAIRED = 4, /* the grid schedule with two pivots per sweep of the full
                                  tableau: the second pivot's entering column, ratio test and
                                  normalised row are formed before the sweep, which then applies
                                  both rank-1 updates to each element (the same roundings as two
                                  sweeps: every output is bitwise identical to the other
                                  schedules), moving about 8 (m+1)(n+m+1) bytes per pivot */
+    LPD_SCHED_GRID_CONDENSED_PAIRED = 5 /* two pivots per sweep of the condensed tableau: both
+                                           savings together, about 8 (m+1)(n+1) bytes per
+                                           pivot, every output bitwise identical */
 } lpd_schedule;
 
 /*

@@ -85,7 +85,7 @@ int resolve_options(const lpd_problem* prob, const lpd_options* opt, SolveArgs* 
     if (opt->eps_d > 0) eps_d = opt->eps_d;
     if (opt->eps_p > 0) eps_p = opt->eps_p;
     if (opt->max_iter >= 0) max_iter = opt->max_iter;
-    if (opt->schedule < LPD_SCHED_AUTO || opt->schedule > LPD_SCHED_GRID_PAIRED) return LPD_ERR_INVALID_ARG;
+    if (opt->schedule < LPD_SCHED_AUTO || opt->schedule > LPD_SCHED_GRID_CONDENSED_PAIRED) return LPD_ERR_INVALID_ARG;
     if (opt->grid_blocks < 0) return LPD_ERR_INVALID_ARG;
     *schedule = opt->schedule;
     *grid_blocks = opt->grid_blocks;
@@ -244,8 +244,8 @@ int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd
   if (schedule == LPD_SCHED_WORKGROUP || (schedule == LPD_SCHED_AUTO && fits_lds))
     return hip_err(launch_wg_solve(a, stream));
 
-  const bool condensed = schedule == LPD_SCHED_GRID_CONDENSED;
-  const bool paired = schedule == LPD_SCHED_GRID_PAIRED;
+  const bool condensed = schedule == LPD_SCHED_GRID_CONDENSED || schedule == LPD_SCHED_GRID_CONDENSED_PAIRED;
+  const bool paired = schedule == LPD_SCHED_GRID_PAIRED || schedule == LPD_SCHED_GRID_CONDENSED_PAIRED;
   const int maxb = grid_max_blocks(a.m, a.n, 0, condensed, paired);
   if (maxb <= 0) return LPD_ERR_TOO_LARGE;
   int nb = grid_blocks > 0 ? grid_blocks : dev.ncu;

@@ -33,8 +33,9 @@ constexpr GridKernel kCondensed = grid_solve_kernel<kNT, 0, true>;
 // Pivot rows longer than the LDS holds: the sweep runs over column panels.
 constexpr GridKernel kPanelled = grid_solve_kernel<kNT, 0, false, true>;
 constexpr GridKernel kPanelledCondensed = grid_solve_kernel<kNT, 0, true, true>;
-// Two pivots per sweep (full tableau, two rows per column panel).
+// Two pivots per sweep (two rows per column panel), full and condensed tableau.
 constexpr GridKernel kPaired = grid_solve_kernel<kNT, 0, false, true, true>;
+constexpr GridKernel kPairedCondensed = grid_solve_kernel<kNT, 0, true, true, true>;
 
 // LPD_GRID_VARIANT (tuning / diagnostics) picks the thread mapping; 0 by default.
 int variant_index(int64_t) {
@@ -44,7 +45,7 @@ int variant_index(int64_t) {
 }
 
 GridKernel pick_kernel(int64_t vw, bool condensed, bool panelled, bool paired = false) {
-  if (paired) return kPaired;
+  if (paired) return condensed ? kPairedCondensed : kPaired;
   if (panelled) return condensed ? kPanelledCondensed : kPanelled;
   return condensed ? kCondensed : kVariants[variant_index(vw)];
 }
@@ -121,8 +122,8 @@ int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed, bool pai
 hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, int nthreads,
                              hipStream_t stream, bool condensed, bool paired) {
   (void)nthreads;
-  // Two pivots per sweep: full tableau, not resumable.
-  if (paired && (condensed || a.state)) return hipErrorInvalidValue;
+  // Two pivots per sweep: not resumable.
+  if (paired && a.state) return hipErrorInvalidValue;
   const GridLayout L = grid_layout(a.m, a.n, nblocks, condensed, paired);
   GridWork w = make_grid_work(L, a.m, workspace);
   const size_t lds = lds_plan(a.m, a.n, &w.cap_cap, &w.lds_vecs, condensed, paired);

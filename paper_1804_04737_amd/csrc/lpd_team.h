@@ -227,7 +227,7 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 // sweep starts (the sweep also rewrites row l and column k1, which P reads).
 template <int NT, int MAP, bool CD = false, bool DYN = true, bool PN = false, bool FU = false>
 __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm, unsigned char* smem) {
-  static_assert(!FU || (PN && !CD), "two pivots per sweep: column panels, full tableau");
+  static_assert(!FU || PN, "two pivots per sweep: column panels");
   Cand* scratch = reinterpret_cast<Cand*>(smem);
   dbl2* prow = reinterpret_cast<dbl2*>(smem + kScratchBytes);
   // Capture list: elements of the entering column met during the sweep.
@@ -446,7 +446,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     const double prhs = gld(rhs_cur + l) / p;
     // Condensed: the variable leaving the basis (row l), which takes over
     // stored column kc.
-    const int32_t vleave = CD ? ((l == lprev) ? kprev : w.basis[l]) : 0;
+    // (Two pivots per sweep write the basis after the pair's barrier, so it
+    // is current here; one pivot per sweep writes it one pivot late.)
+    const int32_t vleave = CD ? ((!FU && l == lprev) ? kprev : w.basis[l]) : 0;
     // Objective row after this pivot, entry v; also stages r_v in LDS.
     auto p_update = [&](int32_t v, dbl2 t, dbl2 o) -> dbl2 {
       dbl2 r, on;
@@ -482,8 +484,9 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     // Two pivots per sweep (FU): the pair's second pivot (k1, l1), its
     // pivot p1, normalised right-hand side prhs1, the first update's
     // multiplier of row l1 (fl1) and that row before the pair (rowl1).
+    // Condensed: k1's stored column kc1 and the variable leaving row l1.
     bool two = false;
-    int32_t l1 = -1;
+    int32_t l1 = -1, k1 = -1, kc1 = -1, vleave1 = -1;
     double p1 = 1.0, prhs1 = 0.0, fl1 = 0.0;
     const dbl2* rowl1 = rowl;
     dbl2* const prt = FU ? own_sreg(reinterpret_cast<dbl2*>(w.prt)) : nullptr;
@@ -516,27 +519,39 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         for (int q = 0; q < 4; ++q) {
           const int32_t v = v0 + q * NT;
           if (v < vw) {
+            // Condensed: stored column kc becomes the leaving variable's
+            // (unit column e_l before the pivot), as in one pivot's P.
+            const bool x_k = CD && 2 * v == kc, y_k = CD && 2 * v + 1 == kc;
             dbl2 r, on;
-            r.x = t[q].x / p;
-            r.y = t[q].y / p;
-            on.x = __builtin_fma(-g, r.x, o[q].x);
-            on.y = __builtin_fma(-g, r.y, o[q].y);
+            r.x = x_k ? 1.0 / p : t[q].x / p;
+            r.y = y_k ? 1.0 / p : t[q].y / p;
+            on.x = __builtin_fma(-g, r.x, x_k ? 0.0 : o[q].x);
+            on.y = __builtin_fma(-g, r.y, y_k ? 0.0 : o[q].y);
             keep_rt(v, r);
             if (v >= pub_v0 && v < pub_v1) gst2(prt + v, r);
-            price_offer(pc1, on.x, 2 * (int64_t)v, ncols);
-            price_offer(pc1, on.y, 2 * (int64_t)v + 1, ncols);
+            if constexpr (CD) {
+              const int2 lb = *reinterpret_cast<const int2*>(w.lab + 2 * v);
+              price_offer_cd(pc1, on.x, x_k ? vleave : lb.x, 2 * v, sc);
+              price_offer_cd(pc1, on.y, y_k ? vleave : lb.y, 2 * v + 1, sc);
+            } else {
+              price_offer(pc1, on.x, 2 * (int64_t)v, ncols);
+              price_offer(pc1, on.y, 2 * (int64_t)v + 1, ncols);
+            }
           }
         }
       }
       pc1 = block_reduce(pc1, scratch);  // also orders the kept row's writes
-      const int32_t k1 = pc1.i;
+      k1 = pc1.i;
+      kc1 = CD ? (int32_t)pc1.aux : pc1.i;
       const double g1 = pc1.v;
-      two = !(pc1.flags & kFlagNonFinite) && !(g1 >= -a.eps_d) && iter + 2 <= a.max_iter;
+      // (Condensed: the leaving variable's reduced cost after the first
+      // pivot, -g/p, is positive, so kc1 != kc whenever k1 is taken.)
+      two = !(pc1.flags & kFlagNonFinite) && !(g1 >= -a.eps_d) && iter + 2 <= a.max_iter && (!CD || kc1 != kc);
       if (two) {
         // Entering column k1 and right-hand side after the first pivot, and
         // the second pivot's ratio test (Step 3), for every row.
-        const dbl2 rk = kept_rt(k1 >> 1);
-        const double rt_k1 = (k1 & 1) ? rk.y : rk.x;
+        const dbl2 rk = kept_rt(kc1 >> 1);
+        const double rt_k1 = (kc1 & 1) ? rk.y : rk.x;
         // This workgroup publishes rows [pa0, pa1) of the column.
         const int32_t pa0 = (int32_t)((int64_t)m * tm.rank / nb), pa1 = (int32_t)((int64_t)m * (tm.rank + 1) / nb);
         const double eps_p = a.eps_p;
@@ -549,7 +564,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           } else {
             const double f = gld(pcol_cur + i);
             const double* rowi = (i == lprev) ? reinterpret_cast<const double*>(pr_prev) : Tm + (int64_t)i * ld;
-            ap = __builtin_fma(-f, rt_k1, gld(rowi + k1));
+            ap = __builtin_fma(-f, rt_k1, gld(rowi + kc1));
             rhp = __builtin_fma(-f, prhs, gld(rhs_cur + i));
           }
           if (i >= pa0 && i < pa1) gst(pap + i, ap);
@@ -565,6 +580,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           const double rhp1 = l1 == l ? prhs : __builtin_fma(-fl1, prhs, gld(rhs_cur + l1));
           prhs1 = rhp1 / p1;
           rowl1 = (l1 == lprev) ? pr_prev : reinterpret_cast<const dbl2*>(Tm + (int64_t)l1 * ld);
+          if constexpr (CD) vleave1 = l1 == l ? k : w.basis[l1];
         }
       }
       // Arrival at the pair's publication barrier: this workgroup's slices of
@@ -589,38 +605,50 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         for (int32_t v = tid; v < vw; v += NT) {
           const dbl2 rt = kept_rt(v);
           const dbl2 o = gld2(obj_cur + v);
+          // Condensed: columns kc and kc1 hold the leaving variables' unit
+          // columns before their pivots.
+          const bool x_k = CD && 2 * v == kc, y_k = CD && 2 * v + 1 == kc;
+          const bool x_k1 = CD && 2 * v == kc1, y_k1 = CD && 2 * v + 1 == kc1;
           dbl2 on, x, r1, on2;
-          on.x = __builtin_fma(-g, rt.x, o.x);
-          on.y = __builtin_fma(-g, rt.y, o.y);
+          on.x = __builtin_fma(-g, rt.x, x_k ? 0.0 : o.x);
+          on.y = __builtin_fma(-g, rt.y, y_k ? 0.0 : o.y);
           if (l1 == l) {
             x = rt;
           } else {
             const dbl2 t1 = gld2(rowl1 + v);
-            x.x = __builtin_fma(-fl1, rt.x, t1.x);
-            x.y = __builtin_fma(-fl1, rt.y, t1.y);
+            x.x = __builtin_fma(-fl1, rt.x, x_k ? 0.0 : t1.x);
+            x.y = __builtin_fma(-fl1, rt.y, y_k ? 0.0 : t1.y);
           }
-          r1.x = x.x / p1;
-          r1.y = x.y / p1;
-          on2.x = __builtin_fma(-g1c, r1.x, on.x);
-          on2.y = __builtin_fma(-g1c, r1.y, on.y);
+          r1.x = x_k1 ? 1.0 / p1 : x.x / p1;
+          r1.y = y_k1 ? 1.0 / p1 : x.y / p1;
+          on2.x = __builtin_fma(-g1c, r1.x, x_k1 ? 0.0 : on.x);
+          on2.y = __builtin_fma(-g1c, r1.y, y_k1 ? 0.0 : on.y);
           if (v >= pub_v0 && v < pub_v1) {
             gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on2);
             gst2(reinterpret_cast<dbl2*>(pr_cur) + v, r1);
           }
-          price_offer(pc2, on2.x, 2 * (int64_t)v, ncols);
-          price_offer(pc2, on2.y, 2 * (int64_t)v + 1, ncols);
+          if constexpr (CD) {
+            const int2 lb = *reinterpret_cast<const int2*>(w.lab + 2 * v);
+            price_offer_cd(pc2, on2.x, x_k1 ? vleave1 : (x_k ? vleave : lb.x), 2 * v, sc);
+            price_offer_cd(pc2, on2.y, y_k1 ? vleave1 : (y_k ? vleave : lb.y), 2 * v + 1, sc);
+          } else {
+            price_offer(pc2, on2.x, 2 * (int64_t)v, ncols);
+            price_offer(pc2, on2.y, 2 * (int64_t)v + 1, ncols);
+          }
         }
         if (leader && tid == 0) {
           const double z1 = __builtin_fma(-g, prhs, gld(rhs_cur + m));
           gst(rhs_nxt + m, __builtin_fma(-g1c, prhs1, z1));
-          const int32_t leaving = w.basis[l];
-          w.pos[leaving] = -1;
-          w.pos[k] = l;
-          w.basis[l] = k;
-          const int32_t leaving1 = w.basis[l1];
-          w.pos[leaving1] = -1;
-          w.pos[k1] = l1;
-          w.basis[l1] = k1;
+          if constexpr (!CD) {  // condensed: after the pair's barrier
+            const int32_t leaving = w.basis[l];
+            w.pos[leaving] = -1;
+            w.pos[k] = l;
+            w.basis[l] = k;
+            const int32_t leaving1 = w.basis[l1];
+            w.pos[leaving1] = -1;
+            w.pos[k1] = l1;
+            w.basis[l1] = k1;
+          }
           if (a.trace) {
             if (iter < a.trace_cap) {
               a.trace[2 * iter] = k;
@@ -639,18 +667,21 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         for (int32_t v = pub_v0 + tid; v < pub_v1; v += NT) {
           const dbl2 rt = kept_rt(v);
           const dbl2 o = gld2(obj_cur + v);
+          const bool x_k = CD && 2 * v == kc, y_k = CD && 2 * v + 1 == kc;
           dbl2 on;
-          on.x = __builtin_fma(-g, rt.x, o.x);
-          on.y = __builtin_fma(-g, rt.y, o.y);
+          on.x = __builtin_fma(-g, rt.x, x_k ? 0.0 : o.x);
+          on.y = __builtin_fma(-g, rt.y, y_k ? 0.0 : o.y);
           gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on);
           gst2(reinterpret_cast<dbl2*>(pr_cur) + v, rt);
         }
         if (leader && tid == 0) {
           gst(rhs_nxt + m, __builtin_fma(-g, prhs, gld(rhs_cur + m)));
-          const int32_t leaving = w.basis[l];
-          w.pos[leaving] = -1;
-          w.pos[k] = l;
-          w.basis[l] = k;
+          if constexpr (!CD) {  // condensed: after the pair's barrier
+            const int32_t leaving = w.basis[l];
+            w.pos[leaving] = -1;
+            w.pos[k] = l;
+            w.basis[l] = k;
+          }
           if (iter < a.trace_cap && a.trace) {
             a.trace[2 * iter] = k;
             a.trace[2 * iter + 1] = l;
@@ -728,12 +759,35 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         __syncthreads();
       }
       if (tk && tid == 0) tk[7] = __builtin_amdgcn_s_memrealtime();
+      if constexpr (CD) {
+        // Condensed: basis, positions and column labels of the sweep's
+        // pivots.  Every workgroup has read the basis and priced with the
+        // labels of this round (all arrived), and the third pass overrides
+        // the labels of columns kc and kc1.
+        if (leader && tid == 0) {
+          w.pos[vleave] = -1;
+          w.pos[k] = l;
+          w.basis[l] = k;
+          w.lab[kc] = vleave;
+          w.col_of[vleave] = kc;
+          w.col_of[k] = -1;
+          if (two) {
+            w.pos[vleave1] = -1;
+            w.pos[k1] = l1;
+            w.basis[l1] = k1;
+            w.lab[kc1] = vleave1;
+            w.col_of[vleave1] = kc1;
+            w.col_of[k1] = -1;
+          }
+        }
+      }
     }
     {
       const int32_t kv = kcn >> 1, kh = kcn & 1;
       // Condensed: stored column kc becomes the leaving variable's column,
       // whose full-tableau entries before the pivot are 0 off row l.
       const int32_t kcv = kc >> 1, kch = kc & 1;
+      const int32_t kc1v = (FU && CD) ? kc1 >> 1 : -1, kc1h = kc1 & 1;  // FU, condensed: the second pivot's column
       const double eps_p = own_sreg(a.eps_p);
       const int64_t ldv = ld / 2;  // row stride in 16-byte vectors
       // One element (i, v) of the dynamic part: the same work as one step of
@@ -779,6 +833,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           if (two) {
             ap = cap2;
             const dbl2 r2 = prow[pvw + v - pv0];
+            if (CD && v == kc1v) {  // the second leaving variable's unit column
+              if (kc1h) nv.y = 0.0;
+              else nv.x = 0.0;
+            }
             if (i == l1) {
               nv = r2;
             } else {
@@ -898,17 +956,19 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
                 // by this sweep.
                 r = gld2(prt + vq);
                 if (two) {
+                  const bool x_k = CD && 2 * vq == kc, y_k = CD && 2 * vq + 1 == kc;
+                  const bool x_k1 = CD && 2 * vq == kc1, y_k1 = CD && 2 * vq + 1 == kc1;
                   dbl2 x;
                   if (l1 == l) {
                     x = r;
                   } else {
                     const dbl2 t1 = gld2(rowl1 + vq);
-                    x.x = __builtin_fma(-fl1, r.x, t1.x);
-                    x.y = __builtin_fma(-fl1, r.y, t1.y);
+                    x.x = __builtin_fma(-fl1, r.x, x_k ? 0.0 : t1.x);
+                    x.y = __builtin_fma(-fl1, r.y, y_k ? 0.0 : t1.y);
                   }
                   dbl2 r1;
-                  r1.x = x.x / p1;
-                  r1.y = x.y / p1;
+                  r1.x = x_k1 ? 1.0 / p1 : x.x / p1;
+                  r1.y = y_k1 ? 1.0 / p1 : x.y / p1;
                   prow[pvw + u] = r1;
                 }
               } else {
@@ -1105,7 +1165,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       a.y[i] = col >= 0 ? obj_f[col] : 0.0;
     }
   if (a.basis_out)
-    for (int64_t i = gid; i < m; i += G) a.basis_out[i] = (CD && i == lprev) ? kprev : w.basis[i];
+    for (int64_t i = gid; i < m; i += G) a.basis_out[i] = (CD && !FU && i == lprev) ? kprev : w.basis[i];
   if (a.tableau_out) {
     const int64_t W = (int64_t)ncols + 1;
     for (int64_t e = gid; e < (int64_t)(m + 1) * W; e += G) {

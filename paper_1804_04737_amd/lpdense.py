@@ -19,6 +19,7 @@ STATUS_NAMES = ("OPTIMAL", "UNBOUNDED", "ITERATION_LIMIT", "INFEASIBLE_START", "
                 "DEVICE_TIMEOUT", "INFEASIBLE")
 ROW_LE, ROW_EQ, ROW_GE = 0, 1, 2
 SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED, SCHED_GRID_PAIRED = 0, 1, 2, 3, 4
+SCHED_GRID_CONDENSED_PAIRED = 5
 
 # Exported symbols, as declared in include/lpdense.h.
 EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lp_solve_general", "lpd_server_create",

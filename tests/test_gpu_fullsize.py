@@ -33,7 +33,8 @@ def test_first_pivots_bitwise(m, n):
     ref = oracle.solve(A, b, c, max_iter=K, want_tableau=True)
     rng = np.random.default_rng(m * 7 + n)
     rows = np.unique(np.concatenate([rng.integers(0, m, 64), ref.trace[:, 1], [m]]))
-    for schedule in (lpdense.SCHED_AUTO, lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED):
+    for schedule in (lpdense.SCHED_AUTO, lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED,
+                     lpdense.SCHED_GRID_CONDENSED_PAIRED):
         g = gpu_solve(A, b, c, max_iter=K, want_tableau=True, schedule=schedule)
         assert g.status == ref.status == oracle.ITERATION_LIMIT
         assert np.array_equal(g.trace, ref.trace)
@@ -58,7 +59,7 @@ def test_full_solve_properties(m, n):
     assert abs(float(c @ g.x) - g.obj) <= 1e-9 * abs(g.obj)
     # The condensed tableau and two pivots per sweep take the same pivots and
     # end with the same bits.
-    for schedule in (lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED):
+    for schedule in (lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED, lpdense.SCHED_GRID_CONDENSED_PAIRED):
         gc = gpu_solve(A, b, c, trace_cap=50 * (m + n), schedule=schedule)
         assert gc.status == g.status and gc.iterations == g.iterations
         assert np.array_equal(gc.trace, g.trace)

@@ -20,13 +20,14 @@ from tests.gpu_util import announce, assert_bitwise_equal, bits, gpu_solve
 pytestmark = pytest.mark.gpu
 
 GRID, CD, PAIR = lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED
+CDPAIR = lpdense.SCHED_GRID_CONDENSED_PAIRED
 LDS_BYTES = 160 * 1024
 # Widest row that fits with a full capture list (scratch + 1024 entries of 20 B).
 ROW_VECS_MAX = (LDS_BYTES - 32 * 24 - 16 - 1024 * 20) // 16
 
 
 def stored_vecs(m, n, schedule):
-    return (n + 1) // 2 if schedule == CD else (n + m + 1) // 2
+    return (n + 1) // 2 if schedule in (CD, CDPAIR) else (n + m + 1) // 2
 
 
 @pytest.mark.parametrize("m,n,blocks,schedule", [
@@ -34,6 +35,7 @@ def stored_vecs(m, n, schedule):
     (40, 45000, 0, GRID), (40, 45000, 3, GRID), (24, 80000, 2, GRID),
     (64, 20000, 0, CD), (64, 20000, 2, CD), (40, 45000, 3, CD),
     (64, 20000, 0, PAIR), (64, 20000, 2, PAIR), (24, 80000, 2, PAIR),
+    (64, 20000, 0, CDPAIR), (40, 45000, 3, CDPAIR), (24, 80000, 2, CDPAIR),
 ], ids=lambda v: str(v))
 def test_panelled_rows_bitwise(m, n, blocks, schedule):
     assert stored_vecs(m, n, schedule) > ROW_VECS_MAX  # the panelled kernel runs

@@ -17,8 +17,9 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
 WG, GRID, CD = lpdense.SCHED_WORKGROUP, lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED
-PAIR = lpdense.SCHED_GRID_PAIRED
-GRIDS = pytest.mark.parametrize("schedule", [GRID, CD, PAIR], ids=["grid", "condensed", "paired"])
+PAIR, CDPAIR = lpdense.SCHED_GRID_PAIRED, lpdense.SCHED_GRID_CONDENSED_PAIRED
+GRIDS = pytest.mark.parametrize("schedule", [GRID, CD, PAIR, CDPAIR],
+                                ids=["grid", "condensed", "paired", "condensed_paired"])
 
 
 def _examples():
@@ -26,7 +27,8 @@ def _examples():
         return json.load(f)["examples"]
 
 
-@pytest.mark.parametrize("schedule", [WG, GRID, CD, PAIR], ids=["wg", "grid", "condensed", "paired"])
+@pytest.mark.parametrize("schedule", [WG, GRID, CD, PAIR, CDPAIR],
+                         ids=["wg", "grid", "condensed", "paired", "condensed_paired"])
 @pytest.mark.parametrize("ex", _examples(), ids=lambda e: e["id"])
 def test_worked_examples(ex, schedule):
     A, b, c = (np.array(ex[k], float) for k in ("A", "b", "c"))
@@ -97,7 +99,8 @@ def test_grid_size_invariance(blocks, schedule):
     assert_bitwise_equal(g, ref, check_tableau=True)
 
 
-@pytest.mark.parametrize("schedule", [WG, GRID, CD, PAIR], ids=["wg", "grid", "condensed", "paired"])
+@pytest.mark.parametrize("schedule", [WG, GRID, CD, PAIR, CDPAIR],
+                         ids=["wg", "grid", "condensed", "paired", "condensed_paired"])
 def test_edge_cases(schedule):
     A = np.array([[1.0, 2.0], [3.0, 1.0]])
     cases = {
@@ -133,7 +136,8 @@ def test_workgroup_and_grid_agree_and_errors():
     assert e.value.code == -7
 
 
-@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, CD, PAIR], ids=["auto", "condensed", "paired"])
+@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, CD, PAIR, CDPAIR],
+                         ids=["auto", "condensed", "paired", "condensed_paired"])
 @pytest.mark.parametrize("m,n,seed", [(1024, 1024, 0), (2048, 512, 1), (512, 2048, 2)])
 def test_medium_full_solve(m, n, seed, schedule):
     A, b, c = lpgen.dense_lp(m, n, seed)
@@ -145,7 +149,8 @@ def test_medium_full_solve(m, n, seed, schedule):
     assert rp <= 1e-9 and rd <= 1e-9 and gap <= 1e-9
 
 
-@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, GRID, CD, PAIR], ids=["auto", "grid", "condensed", "paired"])
+@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, GRID, CD, PAIR, CDPAIR],
+                         ids=["auto", "grid", "condensed", "paired", "condensed_paired"])
 @pytest.mark.parametrize("m,n,seed", [(30, 40, 1), (256, 512, 2), (512, 256, 3), (700, 900, 4)])
 def test_paper_generator_instances(m, n, seed, schedule):
     """The second workload (zeros in A, b = A x0, c of both signs: many
@@ -159,8 +164,10 @@ def test_paper_generator_instances(m, n, seed, schedule):
     assert_bitwise_equal(g, ref, check_tableau=small)
 
 
-@pytest.mark.parametrize("blocks,schedule", [(2, GRID), (3, GRID), (5, GRID), (2, CD), (3, CD), (2, PAIR), (3, PAIR)],
-                         ids=["grid2", "grid3", "grid5", "condensed2", "condensed3", "paired2", "paired3"])
+@pytest.mark.parametrize("blocks,schedule", [(2, GRID), (3, GRID), (5, GRID), (2, CD), (3, CD), (2, PAIR), (3, PAIR),
+                                             (2, CDPAIR), (3, CDPAIR)],
+                         ids=["grid2", "grid3", "grid5", "condensed2", "condensed3", "paired2", "paired3",
+                              "condensed_paired2", "condensed_paired3"])
 def test_dynamic_sweep_bitwise(blocks, schedule):
     """A sweep of at least 48 grid steps hands all but its first 16 steps out
     in chunks through two ticket counters (even and odd chunks); workgroups
