@@ -213,10 +213,6 @@ int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd
                       hipStream_t stream) {
   int rc = validate(prob, out);
   if (rc != LPD_SUCCESS) return rc;
-  DeviceInfo dev;
-  rc = device_info(&dev);
-  if (rc != LPD_SUCCESS) return rc;
-
   SolveArgs a{};
   a.m = prob->m;
   a.n = prob->n;
@@ -224,7 +220,10 @@ int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd
   a.b = prob->b;
   a.c = prob->c;
   int schedule = 0, grid_blocks = 0;
-  rc = resolve_options(prob, opt, &a, &schedule, &grid_blocks);
+  rc = resolve_options(prob, opt, &a, &schedule, &grid_blocks);  // no HIP call before this
+  if (rc != LPD_SUCCESS) return rc;
+  DeviceInfo dev;
+  rc = device_info(&dev);
   if (rc != LPD_SUCCESS) return rc;
   a.x = out->x;
   a.obj = out->obj;

@@ -59,6 +59,13 @@ def test_host_validation_without_device():
     assert lib.lp_solve_dense_ex(ctypes.byref(p), None, ctypes.byref(o), None) == -2  # trace_cap > 0, no trace
     o.trace_cap = -1
     assert lib.lp_solve_dense_ex(ctypes.byref(p), None, ctypes.byref(o), None) == -1
+    # Schedules 0..5 (the last: two pivots per sweep of the condensed tableau);
+    # anything else is an argument error, found before any device call.
+    o.trace_cap = 0
+    assert lpdense.SCHED_GRID_CONDENSED_PAIRED == 5
+    for bad in (-1, 6):
+        opts = lpdense.Options(0.0, 0.0, -1, bad, 0)
+        assert lib.lp_solve_dense_ex(ctypes.byref(p), ctypes.byref(opts), ctypes.byref(o), None) == -1
 
 
 def test_batch_host_validation_without_device():
@@ -121,3 +128,18 @@ def test_python_struct_mirrors_match_the_header():
         want.append(ctypes.sizeof(py))
         want += [getattr(py, f).offset for f, _ in py._fields_]
     assert got == want
+
+
+def test_schedule_constants_match_header():
+    """The binding's schedule numbers are the header's enum values."""
+    with open(HEADER) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    enum = dict((k, int(v)) for k, v in re.findall(r"\b(LPD_SCHED_\w+)\s*=\s*(\d+)", text))
+    assert enum == {
+        "LPD_SCHED_AUTO": lpdense.SCHED_AUTO,
+        "LPD_SCHED_WORKGROUP": lpdense.SCHED_WORKGROUP,
+        "LPD_SCHED_GRID": lpdense.SCHED_GRID,
+        "LPD_SCHED_GRID_CONDENSED": lpdense.SCHED_GRID_CONDENSED,
+        "LPD_SCHED_GRID_PAIRED": lpdense.SCHED_GRID_PAIRED,
+        "LPD_SCHED_GRID_CONDENSED_PAIRED": lpdense.SCHED_GRID_CONDENSED_PAIRED,
+    }
