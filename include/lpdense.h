@@ -166,7 +166,9 @@ typedef struct lpd_outputs {
  * (else LPD_ERR_TOO_LARGE); the grid schedules take any size whose workspace
  * (about 8 (m+1)(n+m+1) bytes, or 8 (m+1)(n+1) condensed) fits in device
  * memory (else LPD_ERR_OUT_OF_MEMORY): a pivot row longer than the LDS holds
- * is swept in column panels, with the same results.
+ * is swept in column panels, with the same results.  The two paired
+ * schedules add one row and one column of the tableau, and one row per
+ * workgroup (m + (nblocks + 1) (n + m + 1) doubles, n + 1 condensed).
  */
 int lp_solve_dense_ex(const lpd_problem *prob, const lpd_options *opt, const lpd_outputs *out,
                       hipStream_t stream);

@@ -215,7 +215,7 @@ __device__ __forceinline__ void ratio_offer(Cand& c, double a, double r, int32_t
 // the sweep runs over column panels of w.lds_vecs vectors, panel after
 // panel, and a workgroup forms the panel of the normalised pivot row it
 // needs from the pivot row itself (same division as in P, so the same bits).
-// FU = true (with PN, full tableau, not resumable) does two pivots per sweep
+// FU = true (with PN, either tableau, not resumable) does two pivots per sweep
 // where it can: the P phase also prices the objective row after the first
 // pivot, forms the entering column of the second after the first update and
 // its ratio test, and the second normalised row; the sweep then applies both
