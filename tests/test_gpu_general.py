@@ -27,8 +27,9 @@ def _check(A, b, c, sense, schedule=lpdense.SCHED_AUTO, max_iter=-1):
     return st
 
 
-@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED],
-                         ids=["auto", "grid", "condensed"])
+@pytest.mark.parametrize("schedule", [lpdense.SCHED_AUTO, lpdense.SCHED_GRID, lpdense.SCHED_GRID_CONDENSED,
+                                      lpdense.SCHED_GRID_PAIRED, lpdense.SCHED_GRID_CONDENSED_PAIRED],
+                         ids=["auto", "grid", "condensed", "paired", "condensed_paired"])
 @pytest.mark.parametrize("m,n,seed", [(3, 4, 0), (20, 15, 3), (120, 90, 5), (300, 400, 6), (700, 500, 7)])
 def test_general_equals_reference(m, n, seed, schedule):
     A, b, c, sense = lpgen.general_lp(m, n, seed)
