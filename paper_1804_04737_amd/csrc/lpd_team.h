@@ -52,7 +52,7 @@ constexpr size_t kScratchBytes = kCandScratch * sizeof(Cand);
 constexpr size_t kCapEntryBytes = 8 + 8 + 4;  // new column entry, new RHS, row
 constexpr int kChunkSteps = 2;                 // dynamic sweep chunk: 2 x NT vectors
 constexpr int kChunkStepsPaired = 3;           // ... with two pivots per sweep
-constexpr int kReadDoneWord = 64;              // ticket region word of the paired sweep's read-done count
+constexpr int kPairCountWord = 64;             // ticket region word counting arrivals at the pair's barrier
 constexpr int64_t kStaticSteps = 16;           // static grid steps before the dynamic part
 constexpr int64_t kDynMinSteps = 48;           // sweeps shorter than this are all static
 
@@ -363,7 +363,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         __hip_atomic_store(w.tickets + h * kTicketStride + 32, (uint32_t)h, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (FU) __hip_atomic_store(w.tickets + kReadDoneWord, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (FU) __hip_atomic_store(w.tickets + kPairCountWord, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     {
       Cand f0 = cand_none();
@@ -593,7 +593,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         __syncthreads();
         if (tid == 0) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          __hip_atomic_fetch_add(w.tickets + kReadDoneWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(w.tickets + kPairCountWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       if (two) {
@@ -743,7 +743,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         if (tid == 0) {
           const uint32_t target = (uint32_t)nb * (uint32_t)(rnd + 1);
           const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-          while ((int32_t)(__hip_atomic_load(w.tickets + kReadDoneWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+          while ((int32_t)(__hip_atomic_load(w.tickets + kPairCountWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
                            target) < 0) {
             __builtin_amdgcn_s_sleep(1);
             if (__builtin_amdgcn_s_memrealtime() - t0 > kWatchdogTicks) {
