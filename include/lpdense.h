@@ -218,8 +218,8 @@ typedef struct lpd_batch_options {
  * tableau is at least team_min_bytes.  Large LPs are started first.  An LP
  * whose pivot row (n + m + 1 doubles, n + 1 condensed) does not fit in LDS
  * beside the reduction scratch (about 20,000 doubles on gfx950) is solved
- * after the batched launch, alone on the grid schedule (as lp_solve_dense_ex,
- * same results), on the same stream.  Returns
+ * after the batched launch, alone on the grid schedule with two pivots per
+ * sweep (as lp_solve_dense_ex, same results), on the same stream.  Returns
  * LPD_SUCCESS or a negative lpd_error; asynchronous and stream-ordered like
  * lp_solve_dense.  Host arrays are only read during the call.
  */

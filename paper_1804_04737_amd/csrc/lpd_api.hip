@@ -331,8 +331,10 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
   knobs.condensed = condensed;
 
   // LPs the batch kernel cannot place (pivot row longer than the LDS holds)
-  // are solved after the batch, one at a time on the grid schedule with its
-  // column panels, on the same stream: the same results as in the batch.
+  // are solved after the batch, one at a time on the grid schedule with two
+  // pivots per sweep and column panels (a batch is not resumed, so the
+  // paired schedule applies), on the same stream: the same results as in the
+  // batch.
   const size_t lds_total = (size_t)batch_lds_total();
   std::vector<int32_t> in_batch, alone;
   for (int32_t i = 0; i < count; ++i)
@@ -359,7 +361,7 @@ int lp_solve_batch(int32_t count, const int64_t* m, const int64_t* n, const doub
     o.eps_d = eps_d;
     o.eps_p = eps_p;
     o.max_iter = max_iter;
-    o.schedule = condensed ? LPD_SCHED_GRID_CONDENSED : LPD_SCHED_GRID;
+    o.schedule = condensed ? LPD_SCHED_GRID_CONDENSED_PAIRED : LPD_SCHED_GRID_PAIRED;
     o.grid_blocks = opt ? opt->grid_blocks : 0;
     lpd_outputs out{};
     out.x = x_pack + x_off[i];

@@ -112,8 +112,8 @@ def test_batch_with_edge_cases(wave_slots):
 def test_batch_with_rows_longer_than_lds(full):
     """The batch kernel walks each LP with its pivot row in LDS.  LPs whose
     row does not fit (10 x 25000, 6 x 40000) are solved after the batch on
-    the grid schedule with column panels; every result, theirs included,
-    equals the oracle's bits."""
+    the grid schedule with two pivots per sweep and column panels; every
+    result, theirs included, equals the oracle's bits."""
     lps = [lpgen.dense_lp(20, 30, 1), lpgen.dense_lp(10, 25000, 2), lpgen.dense_lp(300, 200, 3),
            lpgen.dense_lp(6, 40000, 4), lpgen.dense_lp(64, 64, 5)]
     announce(f"batch with rows longer than the LDS full_tableau={full}")
