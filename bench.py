@@ -284,7 +284,9 @@ def shapes_bench(args):
             A, b, c = gen(m, n, args.seed)
             tA, tb, tc = (torch.from_numpy(v).to(dev) for v in (A, b, c))
             row = {"m": m, "n": n}
-            for name, sched in (("full", lpdense.SCHED_AUTO), ("condensed", lpdense.SCHED_GRID_CONDENSED)):
+            for name, sched in (("full", lpdense.SCHED_AUTO), ("condensed", lpdense.SCHED_GRID_CONDENSED),
+                                ("paired", lpdense.SCHED_GRID_PAIRED),
+                                ("condensed_paired", lpdense.SCHED_GRID_CONDENSED_PAIRED)):
                 lpdense.solve_dense_ex(tA, tb, tc, want_y=False, schedule=sched, stream=stream, max_iter=2)
                 s0 = torch.cuda.Event(enable_timing=True)
                 s1 = torch.cuda.Event(enable_timing=True)
@@ -310,7 +312,7 @@ def shapes_bench(args):
         "steps": len(rows), "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"shape grid m, n in {list(lpgen.PAPER_SIZES)}, {args.generator} generator, "
-                               f"seed {args.seed}, one solve per shape and tableau form (at most 2 (m+n) "
+                               f"seed {args.seed}, one solve per shape and schedule (at most 2 (m+n) "
                                f"pivots); value = all "
                                f"condensed pivots / all condensed time", "shapes": rows},
     }
