@@ -185,3 +185,15 @@ def test_dynamic_sweep_bitwise(blocks, schedule):
     ref = oracle.solve(A, b, c, want_tableau=True)
     assert ref.status == oracle.OPTIMAL
     assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+@GRIDS
+@pytest.mark.parametrize("m,n,seed", [(120, 90, 7), (300, 400, 8)])
+def test_one_workgroup_team(m, n, seed, schedule):
+    """A grid of one workgroup: the team barriers, and the pair's counter
+    barrier on the paired schedules, reduce to workgroup barriers."""
+    A, b, c = lpgen.dense_lp(m, n, seed)
+    announce(f"one-workgroup team {m}x{n} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, grid_blocks=1, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert_bitwise_equal(g, ref, check_tableau=True)
