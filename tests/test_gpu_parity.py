@@ -197,3 +197,33 @@ def test_one_workgroup_team(m, n, seed, schedule):
     g = gpu_solve(A, b, c, schedule=schedule, grid_blocks=1, want_tableau=True)
     ref = oracle.solve(A, b, c, want_tableau=True)
     assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+PAIRS = pytest.mark.parametrize("schedule", [PAIR, CDPAIR], ids=["paired", "condensed_paired"])
+
+
+@PAIRS
+@pytest.mark.parametrize("max_iter", [2, 3, 4, 5, 7])
+def test_pair_iteration_caps(max_iter, schedule):
+    """An odd cap ends on a sweep of one pivot; the tableau at the cap is the
+    oracle's either way."""
+    A, b, c = lpgen.dense_lp(200, 300, 9)
+    announce(f"pair iteration cap {max_iter} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, max_iter=max_iter, want_tableau=True)
+    ref = oracle.solve(A, b, c, max_iter=max_iter, want_tableau=True)
+    assert ref.status == oracle.ITERATION_LIMIT
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
+@PAIRS
+@pytest.mark.parametrize("cap", [1, 4, 5])
+def test_pair_trace_capacity(cap, schedule):
+    """A trace shorter than the solve keeps its first `cap` pivots, also when
+    the capacity ends between the two pivots of a sweep."""
+    A, b, c = lpgen.dense_lp(200, 300, 9)
+    announce(f"pair trace capacity {cap} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, trace_cap=cap)
+    ref = oracle.solve(A, b, c)
+    assert g.iterations == ref.iterations > cap
+    assert np.array_equal(g.trace, ref.trace[:cap])
+    assert np.array_equal(bits(g.x), bits(ref.x))
