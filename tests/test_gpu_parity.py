@@ -110,6 +110,10 @@ def test_edge_cases(schedule):
         "unbounded": (np.array([[0.0, 1.0]]), np.array([1.0]), np.array([1.0, 1.0])),
         "already_optimal": (A, np.array([1.0, 2.0]), np.array([-1.0, 0.0])),
         "degenerate_zero_b": (A, np.array([0.0, 0.0]), np.array([1.0, 1.0])),
+        # the second pivot of a pair finds no eligible row: one pivot, then UNBOUNDED
+        "unbounded_second": (np.array([[1.0, 0.0]]), np.array([1.0]), np.array([2.0, 1.0])),
+        # optimal after the first pivot of a pair
+        "optimal_after_first": (np.array([[1.0, 1.0]]), np.array([1.0]), np.array([1.0, 0.5])),
     }
     for name, (A_, b_, c_) in cases.items():
         announce(f"edge case {name} schedule={schedule}")
