@@ -374,7 +374,10 @@ int lp_solve_general(int64_t m, int64_t n, const double *A, const double *b, con
                      const int8_t *sense, const lpd_options *opt, double *x, double *obj,
                      int32_t *status, int64_t *iterations, hipStream_t stream);
 
-/* Device workspace (bytes) a single solve of an m x n LP allocates. */
+/* Device workspace (bytes) a single solve of an m x n LP allocates on the
+ * default schedule (0 when the tableau fits in one workgroup's LDS).  The
+ * paired schedules take (nblocks + 1) (n + m + 1) + m more doubles (see
+ * lp_solve_dense_ex). */
 uint64_t lpd_workspace_bytes(int64_t m, int64_t n);
 
 /* Static strings for an lpd_error / lpd_status code ("unknown" otherwise). */
