@@ -501,6 +501,10 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       else gst2(priv_rt + v, r);
     };
     auto kept_rt = [&](int32_t v) -> dbl2 { return rt_lds ? prow[v] : gld2(priv_rt + v); };
+    // FU with one panel: both rows of the pair fit side by side in LDS, r_t
+    // at [0, vw) from pass 1 and r1 at [pvw, pvw + vw) from pass 3 (the same
+    // bits as the panel load), so the sweep starts with its panel loaded.
+    const bool one_panel = FU && npan == 1 && rt_lds;
     if constexpr (FU) {
       // Pass 1: first pivot's normalised row (kept, and this workgroup's
       // slice published) and the objective row after it, priced for k1.
@@ -627,6 +631,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
             gst2(reinterpret_cast<dbl2*>(obj_nxt) + v, on2);
             gst2(reinterpret_cast<dbl2*>(pr_cur) + v, r1);
           }
+          if (one_panel) prow[pvw + v] = r1;  // the sweep's only panel, second row
           if constexpr (CD) {
             const int2 lb = *reinterpret_cast<const int2*>(w.lab + 2 * v);
             price_offer_cd(pc2, on2.x, x_k1 ? vleave1 : (x_k ? vleave : lb.x), 2 * v, sc);
@@ -905,7 +910,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
           const uint32_t per = (n_chunks + kTicketCounters - 1) / kTicketCounters;
           return min(n_chunks, h * per);
         };
-        int32_t loaded = -1;
+        int32_t loaded = one_panel ? 0 : -1;  // (pv0 = 0)
         uint32_t jst = 0;
         for (int par = 0;; par ^= 1) {
           uint32_t c;
