@@ -492,7 +492,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     dbl2* const prt = FU ? own_sreg(reinterpret_cast<dbl2*>(w.prt)) : nullptr;
     double* const pap = FU ? own_sreg(w.pap) : nullptr;
     // FU: this workgroup's own copy of r_t for its later passes, in LDS when
-    // the row fits (the sweep's first panel load overwrites it), else in its
+    // the row fits (until the sweep loads a panel over it), else in its
     // private region.
     const bool rt_lds = vw <= w.lds_vecs;
     dbl2* const priv_rt = FU ? reinterpret_cast<dbl2*>(w.priv + (int64_t)tm.rank * w.priv_stride) : nullptr;
