@@ -342,7 +342,7 @@ def main():
                     help="dense / shapes: the main generator, or the paper-style one (zeros in A, b = A x0)")
     ap.add_argument("--schedule", choices=["auto", "condensed", "paired", "condensed_paired"], default="auto",
                     help="dense: full tableau (auto: grid for large LPs), the condensed tableau "
-                         "(nonbasic columns only) or two pivots per sweep of the full tableau; "
+                         "(nonbasic columns only), or two pivots per sweep of either; "
                          "all give bitwise-identical results")
     ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates (LPs/s)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve: timed requests per rate")
