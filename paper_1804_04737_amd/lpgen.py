@@ -52,11 +52,18 @@ def batch_lps(count: int, lo: int = 32, hi: int = 1024, seed: int = 0):
     """
     m, n = batch_shapes(count, lo, hi, seed)
     children = np.random.SeedSequence(seed).spawn(count)
-    out = []
-    for i in range(count):
-        s = int(children[i].generate_state(1, dtype=np.uint64)[0] >> np.uint64(1))
-        out.append(dense_lp(int(m[i]), int(n[i]), s))
-    return out
+    return [dense_lp(int(m[i]), int(n[i]), _child_seed(children[i])) for i in range(count)]
+
+
+def _child_seed(child) -> int:
+    return int(child.generate_state(1, dtype=np.uint64)[0] >> np.uint64(1))
+
+
+def batch_lp(i: int, count: int, lo: int = 32, hi: int = 1024, seed: int = 0):
+    """Instance i of `batch_lps(count, lo, hi, seed)`, drawn on its own."""
+    m, n = batch_shapes(count, lo, hi, seed)
+    child = np.random.SeedSequence(seed).spawn(count)[i]
+    return dense_lp(int(m[i]), int(n[i]), _child_seed(child))
 
 
 def poisson_arrivals(rate: float, count: int, seed: int = 0):

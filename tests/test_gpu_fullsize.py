@@ -1,17 +1,21 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (default grid: one 1024-thread workgroup per CU).
 
-The oracle cannot run thousands of pivots at 8192 x 8192 inside a test, so:
-  * the first K pivots are compared exactly: the GPU and the oracle both run
-    with max_iter = K and return their whole tableaux; sampled rows (plus the
-    objective row and every row that was a pivot row) must agree bit for bit;
-  * the full GPU solve must reproduce the oracle's first K pivots in its
-    trace, end OPTIMAL, and satisfy properties that hold at any size: primal
-    and dual feasibility and a zero duality gap within 1e-9, and
-    complementary slackness;
-  * the condensed-tableau schedule must give the same bits as the full one
-    (first K pivots against the oracle, whole solve against the full path).
+  * The whole solve of every full-size LP (8192 x 8192 with its 3768 pivots,
+    4096 x 4096, 8192 x 1024, 1024 x 8192, 2048 x 8192; generator seed 0) is
+    compared with the oracle's, on all four grid schedules: status, pivot
+    count, every (k, l) of the pivot sequence, the final basis and the bits of
+    x, y and z.  The oracle's results are stored in tests/golden/ by
+    tests/golden/make_oracle_goldens.py, which runs only the CPU oracle (the
+    8192 x 8192 solve takes minutes on the CPU).  The GPU solution must also
+    be primal and dual feasible with a zero duality gap within 1e-9.
+  * The first K pivots are compared element by element: the GPU and the
+    oracle both run with max_iter = K and return their whole tableaux; sampled
+    rows (plus the objective row and every row that was a pivot row) and the
+    whole right-hand side must agree bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -22,6 +26,7 @@ from tests.gpu_util import announce, bits, gpu_solve
 
 pytestmark = pytest.mark.gpu
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 SHAPES = [(8192, 8192), (4096, 4096), (8192, 1024), (1024, 8192), (2048, 8192)]
 
 
@@ -44,24 +49,37 @@ def test_first_pivots_bitwise(m, n):
         del g
 
 
+SCHEDULES = [(lpdense.SCHED_AUTO, "grid"), (lpdense.SCHED_GRID_CONDENSED, "condensed"),
+             (lpdense.SCHED_GRID_PAIRED, "paired"), (lpdense.SCHED_GRID_CONDENSED_PAIRED, "condensed_paired")]
+
+
+def _golden(m, n):
+    path = os.path.join(GOLDEN, f"fullsize_{m}x{n}_seed0.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
 @pytest.mark.parametrize("m,n", SHAPES)
-def test_full_solve_properties(m, n):
+def test_full_solve_equals_oracle(m, n):
     A, b, c = lpgen.dense_lp(m, n, 0)
-    K = 3
-    announce(f"full size {m}x{n}: complete solve")
-    g = gpu_solve(A, b, c, trace_cap=50 * (m + n))
-    ref = oracle.solve(A, b, c, max_iter=K)
-    assert g.status == oracle.OPTIMAL
-    assert np.array_equal(g.trace[:K], ref.trace)
-    rp, rd, gap = lp_checks.residuals(A, b, c, g.x, g.y)
-    assert rp <= 1e-9 and rd <= 1e-9 and gap <= 1e-9, (rp, rd, gap)
-    assert lp_checks.complementary_slackness(A, b, c, g.x, g.y) <= 1e-9
-    assert abs(float(c @ g.x) - g.obj) <= 1e-9 * abs(g.obj)
-    # The condensed tableau and two pivots per sweep take the same pivots and
-    # end with the same bits.
-    for schedule in (lpdense.SCHED_GRID_CONDENSED, lpdense.SCHED_GRID_PAIRED, lpdense.SCHED_GRID_CONDENSED_PAIRED):
-        gc = gpu_solve(A, b, c, trace_cap=50 * (m + n), schedule=schedule)
-        assert gc.status == g.status and gc.iterations == g.iterations
-        assert np.array_equal(gc.trace, g.trace)
-        assert np.array_equal(bits(gc.x), bits(g.x)) and np.array_equal(bits(gc.y), bits(g.y))
-        assert bits([gc.obj])[0] == bits([g.obj])[0] and np.array_equal(gc.basis, g.basis)
+    ref = _golden(m, n)
+    assert int(ref["m"]) == m and int(ref["n"]) == n and int(ref["status"]) == oracle.OPTIMAL
+    K = int(ref["iterations"])
+    for schedule, name in SCHEDULES:
+        announce(f"full size {m}x{n}: complete solve, {name} schedule, against the oracle's {K} pivots")
+        g = gpu_solve(A, b, c, trace_cap=50 * (m + n), schedule=schedule)
+        assert g.status == int(ref["status"]), (name, g.status)
+        assert g.iterations == K, (name, g.iterations, K)
+        if not np.array_equal(g.trace, ref["trace"]):
+            bad = int(np.argmax(np.any(g.trace != ref["trace"], axis=1)))
+            raise AssertionError(f"{name}: pivot {bad} differs: gpu {g.trace[bad]} oracle {ref['trace'][bad]}")
+        assert np.array_equal(g.basis.astype(np.int64), ref["basis"].astype(np.int64)), name
+        assert np.array_equal(bits(g.x), ref["x_bits"]), name
+        assert np.array_equal(bits(g.y), ref["y_bits"]), name
+        assert bits([g.obj])[0] == int(ref["obj_bits"][0]), name
+        if schedule == lpdense.SCHED_AUTO:
+            # Properties that hold at any size, from the original data.
+            rp, rd, gap = lp_checks.residuals(A, b, c, g.x, g.y)
+            assert rp <= 1e-9 and rd <= 1e-9 and gap <= 1e-9, (rp, rd, gap)
+            assert lp_checks.complementary_slackness(A, b, c, g.x, g.y) <= 1e-9
+        del g
