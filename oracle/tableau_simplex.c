@@ -42,11 +42,23 @@
  *    ratio test, ends the solve with status NUMERICAL; a negative b_i ends it
  *    with INFEASIBLE_START (no pivot), since Step 1's slack basis needs b>=0.
  *
+ * Besides the solve from Table 1 (oracle_solve), the file offers the same
+ * Steps 2-5 from any basic tableau (oracle_solve_tableau), one pivot on a
+ * given element (oracle_pivot: Steps 4-5 alone) and the elimination of the
+ * basic columns from the objective row (oracle_price_out: Step 5 applied to
+ * the objective row with each basic row as pivot row).  The two-phase method
+ * for general LPs (oracle/general.py) is composed of these.
+ *
  * Build: gcc -O3 -mavx2 -std=c11 -mfma -ffp-contract=off -fno-math-errno -shared -fPIC
  * (-ffp-contract=off: the only fused operation is the explicit fma() call.)
+ * Built with -fopenmp as well, Step 5 runs its rows in parallel threads; the
+ * rows are independent, so every value is the same as in the serial build.
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -89,6 +101,100 @@ static void extract(int64_t m, int64_t n, const double *T, const int64_t *basis,
     if (obj) *obj = TAB(T, W, m, W - 1);
     if (y)
         for (int64_t i = 0; i < m; ++i) y[i] = TAB(T, W, m, n + i);
+}
+
+/* Steps 4-5 for the pivot element (l, k): divide row l by T[l,k], then
+ * eliminate column k from every other row of the R-row tableau, the
+ * objective row included; the multiplier is read before the row changes. */
+static void pivot_on(int64_t R, int64_t W, double *T, int64_t l, int64_t k) {
+    /* Step 4: divide the pivot row by the pivot element. */
+    const double p = TAB(T, W, l, k);
+    for (int64_t j = 0; j < W; ++j) TAB(T, W, l, j) = TAB(T, W, l, j) / p;
+
+    /* Step 5: eliminate column k from every other row, objective row
+     * included; the multiplier is read before the row is changed. */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < R; ++i) {
+        if (i == l) continue;
+        const double f = TAB(T, W, i, k);
+        for (int64_t j = 0; j < W; ++j)
+            TAB(T, W, i, j) = fma(-f, TAB(T, W, l, j), TAB(T, W, i, j));
+    }
+}
+
+/* Steps 2-5 repeated (Section 3's loop) on the tableau T of m constraint
+ * rows and the objective row m, with ncols variable columns and the RHS in
+ * column ncols; basis[i] is the variable of row i.  Stops at a status;
+ * returns it and leaves the final tableau and basis in place. */
+static int iterate(int64_t m, int64_t ncols, double *T, int64_t *basis, double eps_d,
+                   double eps_p, int64_t max_iter, int64_t *iters, int32_t *trace,
+                   int64_t trace_cap) {
+    const int64_t R = m + 1, W = ncols + 1;
+    int status = -1;
+    int64_t iter = 0;
+    while (status < 0) {
+        /* Step 2: entering column = most negative reduced cost, lowest index
+         * on ties (strict < in a left-to-right scan). */
+        int64_t k = -1;
+        double best = INFINITY;
+        int bad = 0;
+        for (int64_t j = 0; j < ncols; ++j) {
+            const double v = TAB(T, W, m, j);
+            if (!isfinite(v)) bad = 1;
+            if (v < best) {
+                best = v;
+                k = j;
+            }
+        }
+        if (bad || k < 0) {
+            status = ORC_NUMERICAL;
+            break;
+        }
+        if (best >= -eps_d) {
+            status = ORC_OPTIMAL;
+            break;
+        }
+        if (iter == max_iter) {
+            status = ORC_ITERATION_LIMIT;
+            break;
+        }
+
+        /* Step 3: min-ratio test over the rows with a positive entry in
+         * column k; lowest row index on ties. */
+        int64_t l = -1;
+        double best_rho = INFINITY;
+        for (int64_t i = 0; i < m; ++i) {
+            const double a = TAB(T, W, i, k), r = TAB(T, W, i, W - 1);
+            if (!isfinite(a) || !isfinite(r)) bad = 1;
+            if (a > eps_p) {
+                const double rho = r / a;
+                if (l < 0 || rho < best_rho) {
+                    best_rho = rho;
+                    l = i;
+                }
+            }
+        }
+        if (bad) {
+            status = ORC_NUMERICAL;
+            break;
+        }
+        if (l < 0) {
+            status = ORC_UNBOUNDED;
+            break;
+        }
+
+        /* Steps 4-5. */
+        pivot_on(R, W, T, l, k);
+
+        basis[l] = k;
+        if (trace && iter < trace_cap) {
+            trace[2 * iter] = (int32_t)k;
+            trace[2 * iter + 1] = (int32_t)l;
+        }
+        ++iter;
+    }
+    if (iters) *iters = iter;
+    return status;
 }
 
 /*
@@ -134,77 +240,8 @@ int oracle_solve(int64_t m, int64_t n, const double *A, const double *b,
     for (int64_t i = 0; i < m && status < 0; ++i)
         if (b[i] < 0.0) status = ORC_INFEASIBLE_START;
 
-    while (status < 0) {
-        /* Step 2: entering column = most negative reduced cost, lowest index
-         * on ties (strict < in a left-to-right scan). */
-        int64_t k = -1;
-        double best = INFINITY;
-        int bad = 0;
-        for (int64_t j = 0; j < n + m; ++j) {
-            const double v = TAB(T, W, m, j);
-            if (!isfinite(v)) bad = 1;
-            if (v < best) {
-                best = v;
-                k = j;
-            }
-        }
-        if (bad || k < 0) {
-            status = ORC_NUMERICAL;
-            break;
-        }
-        if (best >= -eps_d) {
-            status = ORC_OPTIMAL;
-            break;
-        }
-        if (iter == max_iter) {
-            status = ORC_ITERATION_LIMIT;
-            break;
-        }
-
-        /* Step 3: min-ratio test over the rows with a positive entry in
-         * column k; lowest row index on ties. */
-        int64_t l = -1;
-        double best_rho = INFINITY;
-        for (int64_t i = 0; i < m; ++i) {
-            const double a = TAB(T, W, i, k), r = TAB(T, W, i, W - 1);
-            if (!isfinite(a) || !isfinite(r)) bad = 1;
-            if (a > eps_p) {
-                const double rho = r / a;
-                if (l < 0 || rho < best_rho) {
-                    best_rho = rho;
-                    l = i;
-                }
-            }
-        }
-        if (bad) {
-            status = ORC_NUMERICAL;
-            break;
-        }
-        if (l < 0) {
-            status = ORC_UNBOUNDED;
-            break;
-        }
-
-        /* Step 4: divide the pivot row by the pivot element. */
-        const double p = TAB(T, W, l, k);
-        for (int64_t j = 0; j < W; ++j) TAB(T, W, l, j) = TAB(T, W, l, j) / p;
-
-        /* Step 5: eliminate column k from every other row, objective row
-         * included; the multiplier is read before the row is changed. */
-        for (int64_t i = 0; i < R; ++i) {
-            if (i == l) continue;
-            const double f = TAB(T, W, i, k);
-            for (int64_t j = 0; j < W; ++j)
-                TAB(T, W, i, j) = fma(-f, TAB(T, W, l, j), TAB(T, W, i, j));
-        }
-
-        basis[l] = k;
-        if (trace && iter < trace_cap) {
-            trace[2 * iter] = (int32_t)k;
-            trace[2 * iter + 1] = (int32_t)l;
-        }
-        ++iter;
-    }
+    if (status < 0)
+        status = iterate(m, n + m, T, basis, eps_d, eps_p, max_iter, &iter, trace, trace_cap);
 
     extract(m, n, T, basis, x, obj, y);
     if (iters) *iters = iter;
@@ -213,4 +250,66 @@ int oracle_solve(int64_t m, int64_t n, const double *A, const double *b,
     free(T);
     free(basis);
     return status;
+}
+
+/*
+ * oracle_solve_tableau: Steps 2-5 from a given basic tableau instead of
+ * Table 1, in place.
+ *   m      constraint rows (>= 0); the objective row is row m
+ *   ncols  variable columns (>= 1); the RHS is column ncols, so T is
+ *          (m+1) x (ncols+1) row-major
+ *   basis  m entries: the variable (column) of each row, whose column must
+ *          be the unit vector of that row with a zero objective-row entry;
+ *          updated in place
+ * The right-hand side is used as stored.  A non-finite entry anywhere in T
+ * gives NUMERICAL before any pivot.  iters and trace as in oracle_solve.
+ * Returns the status or a negative error code.
+ */
+int oracle_solve_tableau(int64_t m, int64_t ncols, double *T, int64_t *basis, double eps_d,
+                         double eps_p, int64_t max_iter, int64_t *iters, int32_t *trace,
+                         int64_t trace_cap) {
+    if (m < 0 || ncols < 1 || !T || (m > 0 && !basis) || max_iter < 0) return ORC_ERR_ARG;
+    const int64_t W = ncols + 1;
+    for (int64_t e = 0; e < (m + 1) * W; ++e)
+        if (!isfinite(T[e])) {
+            if (iters) *iters = 0;
+            return ORC_NUMERICAL;
+        }
+    return iterate(m, ncols, T, basis, eps_d, eps_p, max_iter, iters, trace, trace_cap);
+}
+
+/* oracle_pivot: Steps 4-5 alone, on the element (l, k) of the
+ * (m+1) x (ncols+1) tableau T (any nonzero T[l,k], either sign), in place. */
+int oracle_pivot(int64_t m, int64_t ncols, double *T, int64_t l, int64_t k) {
+    if (m < 1 || ncols < 1 || !T || l < 0 || l >= m || k < 0 || k >= ncols) return ORC_ERR_ARG;
+    pivot_on(m + 1, ncols + 1, T, l, k);
+    return 0;
+}
+
+/* oracle_price_out: makes the objective row (row m) zero in every basic
+ * column, as Step 5 does when a column enters: for each row i in ascending
+ * order, with f the objective-row entry of basis[i]'s column, if f != 0 the
+ * objective row becomes fma(-f, row i, objective row), element by element
+ * over all ncols+1 columns (row i holds 1 in that column). */
+int oracle_price_out(int64_t m, int64_t ncols, double *T, const int64_t *basis) {
+    if (m < 0 || ncols < 1 || !T || (m > 0 && !basis)) return ORC_ERR_ARG;
+    const int64_t W = ncols + 1;
+    for (int64_t i = 0; i < m; ++i) {
+        const double g = TAB(T, W, m, basis[i]);
+        if (g == 0.0) continue;
+        for (int64_t j = 0; j < W; ++j) TAB(T, W, m, j) = fma(-g, TAB(T, W, i, j), TAB(T, W, m, j));
+    }
+    return 0;
+}
+
+/* oracle_threads: with the OpenMP build, sets the number of threads Step 5
+ * uses (n > 0); returns the number it will use (1 in the serial build). */
+int oracle_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

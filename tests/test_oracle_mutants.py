@@ -23,7 +23,7 @@ MUTANTS = {
     "fma_sign": ("fma(-f, TAB(T, W, l, j)", "fma(f, TAB(T, W, l, j)"),
     "pricing_tie_highest": ("if (v < best) {", "if (v <= best) {"),
     "ratio_tie_highest": ("rho < best_rho", "rho <= best_rho"),
-    "objective_row_skipped": ("for (int64_t i = 0; i < R; ++i) {", "for (int64_t i = 0; i < m; ++i) {"),
+    "objective_row_skipped": ("for (int64_t i = 0; i < R; ++i) {", "for (int64_t i = 0; i < R - 1; ++i) {"),
     "negative_entries_eligible": ("if (a > eps_p) {", "if (a != 0.0) {"),
     "no_normalisation": ("TAB(T, W, l, j) = TAB(T, W, l, j) / p;", "TAB(T, W, l, j) = TAB(T, W, l, j);"),
     "slack_identity_misplaced": ("TAB(T, W, i, n + i) = 1.0;", "TAB(T, W, i, n) = 1.0;"),
@@ -31,7 +31,7 @@ MUTANTS = {
     "cost_sign": ("TAB(T, W, m, j) = -c[j];", "TAB(T, W, m, j) = c[j];"),
     "dual_wrong_column": ("y[i] = TAB(T, W, m, n + i);", "y[i] = TAB(T, W, m, i);"),
     "ratio_transposed": ("const double rho = r / a;", "const double rho = a / r;"),
-    "pricing_skips_slacks": ("for (int64_t j = 0; j < n + m; ++j) {", "for (int64_t j = 0; j < n; ++j) {"),
+    "pricing_skips_slacks": ("for (int64_t j = 0; j < ncols; ++j) {", "for (int64_t j = 0; j < ncols - m; ++j) {"),
     "multiplier_from_pivot_row": ("const double f = TAB(T, W, i, k);", "const double f = TAB(T, W, l, k);"),
 }
 
