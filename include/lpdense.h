@@ -331,38 +331,80 @@ int lpd_server_get_stats(lpd_server *server, lpd_server_stats *out);
 void lpd_server_destroy(lpd_server *server);
 
 /*
+ * lp_solve_tableau: Steps 2-5 (Section 2, iterated as in Section 3) from a
+ * given basic tableau instead of Table 1: a warm start from any basis, and
+ * the building block of lp_solve_general's two phases.
+ *   m       constraint rows (>= 1, host)
+ *   ncols   variable columns (>= m, host).  The tableau has m + 1 rows, the
+ *           last being the objective row in Table 1's sign convention
+ *           (reduced costs, minimised by pricing; its RHS is the objective
+ *           value), and ncols + 1 columns, the last being the RHS.
+ *   T0      (m+1) x (ncols+1) row-major (device, read only; not modified)
+ *   basis0  HOST array of m column indices, the basic variable of each row:
+ *           distinct and in [0, ncols) (else LPD_ERR_INVALID_ARG, nothing
+ *           enqueued); read during the call only.  Each one's column must be
+ *           the unit vector of its row with objective-row entry 0 (not
+ *           checked: the caller states a basic tableau).
+ *   opt     as lp_solve_dense_ex; the default iteration cap is 50 ncols
+ *   out     x: ncols entries, the value of every column's variable (its
+ *           row's RHS if basic, else 0); obj: the objective row's final RHS;
+ *           status, iterations, trace ((k, l) with k a column of T0), basis
+ *           (m), tableau ((m+1) x (ncols+1)), phase_ticks: as in
+ *           lp_solve_dense_ex; y must be NULL (LPD_ERR_INVALID_ARG).
+ * The right-hand side is used as stored, with no sign check (a start that is
+ * not primal feasible is the caller's choice).  A non-finite entry anywhere
+ * in T0 gives LPD_NUMERICAL with no pivot.  Every schedule applies: on the
+ * condensed ones the stored columns are the nonbasic ones in increasing
+ * order, pricing ties still go to the lowest column of T0, and all outputs
+ * are bitwise those of the full tableau.  Asynchronous and stream-ordered
+ * like lp_solve_dense_ex (the index arrays derived from basis0 are copied to
+ * the device on `stream`).
+ */
+int lp_solve_tableau(int64_t m, int64_t ncols, const double *T0, const int64_t *basis0,
+                     const lpd_options *opt, const lpd_outputs *out, hipStream_t stream);
+
+/*
  * General LPs (two-phase method).  Section 2 states the problem with rows
  * A x = b and treats the canonical <= form with b >= 0, where the slack basis
  * is a feasible start.  lp_solve_general accepts rows of any sense and
  * right-hand sides of any sign:
  *
- *     maximize c^T x  subject to  A_i x (<=, =, >=) b_i,  x >= 0.
+ *     maximize c^T x  subject to  A_i x (<=, =, >=) b_i,  x >= 0,
  *
- * Phase I: every row is scaled by +1 or -1 so that its right-hand side is
- * >= 0; a row that then reads ">=" gets a surplus column, and every row
- * whose slack cannot start basic (">=" or "=") gets an artificial variable
- * as its basic variable.  That is an LP of the canonical form above with n +
- * (number of surplus columns) structural variables, whose objective is the
- * sum of the artificial rows; it is solved by the pivot kernels of
- * lp_solve_dense_ex.  The LP is feasible iff that optimum reaches the sum of
- * the artificial rows' right-hand sides (relative tolerance 1e-9); else the
- * status is LPD_INFEASIBLE.
- * Phase II restarts from phase I's final basis: the nonbasic non-artificial
- * columns of phase I's final tableau become the structural columns of a
- * second canonical LP, whose slack basis is phase I's basis, with the
- * original costs reduced by that basis (c_N - A_N^T c_B, one sequential sum
- * per column); an artificial variable that stays basic at level zero gets a
- * mirrored row so that it stays zero.  The second solve gives the optimum;
- * x of the original variables is read back, and obj = c^T x.
+ * by the textbook two-phase method on the pivot kernels (lp_solve_tableau):
+ *  1. Row i is multiplied by -1 when b_i < 0, or when b_i = 0 and the row
+ *     reads >=, so that every right-hand side is >= 0.
+ *  2. Columns, in Table 1's layout: the n variables; one surplus column (-1)
+ *     per row that now reads >=, in row order; one column per row holding
+ *     the variable that starts basic there: its slack (<= rows) or an
+ *     artificial variable (>= and = rows); the RHS.
+ *  3. Phase I maximises minus the sum of the artificial variables: the
+ *     objective row is +1 in the artificial columns, those basic columns
+ *     then eliminated from it (Step 5 on the objective row, rows in order).
+ *     Steps 2-5 run to a status.
+ *  4. The LP is feasible iff phase I ends optimal at a value >= -1e-9 *
+ *     max(1, sum of the artificial rows' right-hand sides); else the status
+ *     is LPD_INFEASIBLE.
+ *  5. Each artificial variable still basic (rows in order) is driven out by
+ *     a pivot (Steps 4-5) on the lowest non-artificial column whose entry in
+ *     its row exceeds eps_p in magnitude; a row with none is redundant.
+ *  6. Phase II: the artificial columns and the redundant rows are deleted,
+ *     the objective row becomes [-c | 0 | 0] with the basic columns
+ *     eliminated from it, and Steps 2-5 run to a status.
+ *  7. x_j is the RHS of x_j's row if basic, else 0; obj is the objective
+ *     row's RHS.  When phase II is not reached, x is phase I's and obj =
+ *     sum_j c_j x_j in index order.
  *
  *   m, n        sizes (host)
  *   A, b, c     device arrays, as lp_solve_dense (b of any sign)
  *   sense       host array of m lpd_row_sense values, or NULL for all <=
  *   opt         may be NULL; schedule, eps and max_iter apply to each phase
+ *               (default cap 50 (m + n) per phase)
  *   x, obj, status  device outputs (x: n entries)
- *   iterations  optional device output: pivots of both phases
- * Unlike the other solve calls this one synchronises `stream`: the phase II
- * layout depends on phase I's basis.  Returns LPD_SUCCESS or an lpd_error.
+ *   iterations  optional device output: pivots of phase I, of the drive-out
+ *               and of phase II
+ * Unlike the other solve calls this one synchronises `stream`: the layout of
+ * phase II depends on phase I's basis.  Returns LPD_SUCCESS or an lpd_error.
  */
 typedef enum lpd_row_sense {
     LPD_ROW_LE = 0,

@@ -192,6 +192,154 @@ int run_batch(BatchPlan& P, const std::vector<int32_t>& idx, const int64_t* m, c
   return hip_err(ef);
 }
 
+
+// Index arrays of a start from a given basic tableau, laid out as
+// [basis (m) | pos (ncols) | lab (n + 1) | colof (ncols)] (lab and colof for
+// the condensed tableau only, n = ncols - m), built on the host and copied
+// to the device in front of the solve.  The host copy is released by a host
+// function enqueued after the copy, so the call stays asynchronous.
+struct StartIndex {
+  std::vector<int32_t> v;
+  int64_t off_pos = 0, off_lab = 0, off_colof = 0;
+};
+
+void release_start_index(void* p) { delete static_cast<StartIndex*>(p); }
+
+StartIndex* start_index(int64_t m, int64_t ncols, const int64_t* basis0, bool condensed) {
+  const int64_t n = ncols - m;
+  auto* s = new StartIndex;
+  s->off_pos = m;
+  s->off_lab = m + ncols;
+  s->off_colof = s->off_lab + (condensed ? n + 1 : 0);
+  s->v.assign((size_t)(s->off_colof + (condensed ? ncols : 0)), -1);
+  for (int64_t i = 0; i < m; ++i) {
+    s->v[(size_t)i] = (int32_t)basis0[i];
+    s->v[(size_t)(s->off_pos + basis0[i])] = (int32_t)i;
+  }
+  if (condensed) {
+    int64_t c = 0;
+    for (int64_t j = 0; j < ncols; ++j)
+      if (s->v[(size_t)(s->off_pos + j)] < 0) {
+        s->v[(size_t)(s->off_lab + c)] = (int32_t)j;
+        s->v[(size_t)(s->off_colof + j)] = (int32_t)c;
+        ++c;
+      }
+  }
+  return s;
+}
+
+// Copies a start's index arrays to `dev` (stream-ordered) and points the
+// solve's arguments at them; takes ownership of `si`.
+hipError_t upload_start_index(StartIndex* si, int32_t* dev, SolveArgs& a, bool condensed, hipStream_t stream) {
+  hipError_t e = hipMemcpyAsync(dev, si->v.data(), si->v.size() * 4, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipLaunchHostFunc(stream, release_start_index, si);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(stream);
+    delete si;
+    return e;
+  }
+  a.basis0 = dev;
+  a.pos0 = dev + si->off_pos;
+  a.lab0 = condensed ? dev + si->off_lab : nullptr;
+  a.colof0 = condensed ? dev + si->off_colof : nullptr;
+  return hipSuccess;
+}
+
+// Runs the solve described by `a` (inputs, options and outputs set) on
+// `schedule`, its workspace allocated stream-ordered on `stream`.  `basis0`
+// (host, m entries) starts from the tableau a.T0 instead of Table 1.
+int run_solve(SolveArgs& a, int schedule, int grid_blocks, const int64_t* basis0, hipStream_t stream) {
+  DeviceInfo dev;
+  int rc = device_info(&dev);
+  if (rc != LPD_SUCCESS) return rc;
+  const int64_t ncols = a.m + a.n;
+  const bool fits_lds = wg_lds_bytes(a.m, a.n) <= wg_lds_limit();
+  if (schedule == LPD_SCHED_WORKGROUP && !fits_lds) return LPD_ERR_TOO_LARGE;
+  if (schedule == LPD_SCHED_WORKGROUP || (schedule == LPD_SCHED_AUTO && fits_lds)) {
+    if (!basis0) return hip_err(launch_wg_solve(a, stream));
+    StartIndex* si = start_index(a.m, ncols, basis0, false);
+    void* meta = nullptr;
+    hipError_t e = hipMallocAsync(&meta, si->v.size() * 4, stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      delete si;
+      return hip_err(e);
+    }
+    e = upload_start_index(si, static_cast<int32_t*>(meta), a, false, stream);
+    if (e == hipSuccess) e = launch_wg_solve(a, stream);
+    const hipError_t ef = hipFreeAsync(meta, stream);
+    return hip_err(e != hipSuccess ? e : ef);
+  }
+
+  // A tableau with no nonbasic column has nothing to store condensed: the
+  // full-tableau schedules give the same results.
+  bool condensed = schedule == LPD_SCHED_GRID_CONDENSED || schedule == LPD_SCHED_GRID_CONDENSED_PAIRED;
+  const bool paired = schedule == LPD_SCHED_GRID_PAIRED || schedule == LPD_SCHED_GRID_CONDENSED_PAIRED;
+  if (a.n == 0) condensed = false;
+  const int maxb = grid_max_blocks(a.m, a.n, 0, condensed, paired);
+  if (maxb <= 0) return LPD_ERR_TOO_LARGE;
+  int nb = grid_blocks > 0 ? grid_blocks : dev.ncu;
+  if (nb > maxb) nb = maxb;
+  const GridLayout L = grid_layout(a.m, a.n, nb, condensed, paired);
+  StartIndex* si = basis0 ? start_index(a.m, ncols, basis0, condensed) : nullptr;
+  const uint64_t meta_bytes = si ? (uint64_t)si->v.size() * 4 : 0;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && L.total + meta_bytes > total_b) {
+    delete si;
+    return LPD_ERR_OUT_OF_MEMORY;
+  }
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, L.total + meta_bytes, stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete si;
+    return hip_err(e);
+  }
+  if (si)
+    e = upload_start_index(si, reinterpret_cast<int32_t*>(static_cast<unsigned char*>(ws) + L.total), a, condensed,
+                           stream);
+  if (e == hipSuccess) e = launch_grid_solve(a, ws, nb, 0, stream, condensed, paired);
+  const hipError_t ef = hipFreeAsync(ws, stream);
+  if (e != hipSuccess) return hip_err(e);
+  return hip_err(ef);
+}
+
+// Outputs of a solve into its kernel arguments (validated by the caller).
+int bind_outputs(const lpd_outputs* out, SolveArgs* a) {
+  a->x = out->x;
+  a->obj = out->obj;
+  a->status = out->status;
+  a->y = out->y;
+  a->iterations = out->iterations;
+  a->trace = out->trace_cap > 0 ? out->trace : nullptr;
+  a->trace_cap = out->trace_cap;
+  a->basis_out = out->basis;
+  a->tableau_out = out->tableau;
+  if (out->phase_cap < 0 || (out->phase_cap > 0 && !out->phase_ticks)) return LPD_ERR_INVALID_ARG;
+  a->phase_ticks = out->phase_cap > 0 ? out->phase_ticks : nullptr;
+  a->phase_cap = out->phase_cap;
+  return LPD_SUCCESS;
+}
+
+// lp_solve_dense_ex.
+int solve_dense(const lpd_problem* prob, const lpd_options* opt, const lpd_outputs* out, hipStream_t stream) {
+  int rc = validate(prob, out);
+  if (rc != LPD_SUCCESS) return rc;
+  SolveArgs a{};
+  a.m = prob->m;
+  a.n = prob->n;
+  a.A = prob->A;
+  a.b = prob->b;
+  a.c = prob->c;
+  int schedule = 0, grid_blocks = 0;
+  rc = resolve_options(prob, opt, &a, &schedule, &grid_blocks);  // no HIP call before this
+  if (rc != LPD_SUCCESS) return rc;
+  rc = bind_outputs(out, &a);
+  if (rc != LPD_SUCCESS) return rc;
+  return run_solve(a, schedule, grid_blocks, nullptr, stream);
+}
+
 }  // namespace
 
 BatchKnobs tuned_batch_knobs() {
@@ -211,57 +359,36 @@ extern "C" {
 
 int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd_outputs* out,
                       hipStream_t stream) {
-  int rc = validate(prob, out);
-  if (rc != LPD_SUCCESS) return rc;
-  SolveArgs a{};
-  a.m = prob->m;
-  a.n = prob->n;
-  a.A = prob->A;
-  a.b = prob->b;
-  a.c = prob->c;
-  int schedule = 0, grid_blocks = 0;
-  rc = resolve_options(prob, opt, &a, &schedule, &grid_blocks);  // no HIP call before this
-  if (rc != LPD_SUCCESS) return rc;
-  DeviceInfo dev;
-  rc = device_info(&dev);
-  if (rc != LPD_SUCCESS) return rc;
-  a.x = out->x;
-  a.obj = out->obj;
-  a.status = out->status;
-  a.y = out->y;
-  a.iterations = out->iterations;
-  a.trace = out->trace_cap > 0 ? out->trace : nullptr;
-  a.trace_cap = out->trace_cap;
-  a.basis_out = out->basis;
-  a.tableau_out = out->tableau;
-  if (out->phase_cap < 0 || (out->phase_cap > 0 && !out->phase_ticks)) return LPD_ERR_INVALID_ARG;
-  a.phase_ticks = out->phase_cap > 0 ? out->phase_ticks : nullptr;
-  a.phase_cap = out->phase_cap;
+  return solve_dense(prob, opt, out, stream);
+}
 
-  const bool fits_lds = wg_lds_bytes(a.m, a.n) <= wg_lds_limit();
-  if (schedule == LPD_SCHED_WORKGROUP && !fits_lds) return LPD_ERR_TOO_LARGE;
-  if (schedule == LPD_SCHED_WORKGROUP || (schedule == LPD_SCHED_AUTO && fits_lds))
-    return hip_err(launch_wg_solve(a, stream));
-
-  const bool condensed = schedule == LPD_SCHED_GRID_CONDENSED || schedule == LPD_SCHED_GRID_CONDENSED_PAIRED;
-  const bool paired = schedule == LPD_SCHED_GRID_PAIRED || schedule == LPD_SCHED_GRID_CONDENSED_PAIRED;
-  const int maxb = grid_max_blocks(a.m, a.n, 0, condensed, paired);
-  if (maxb <= 0) return LPD_ERR_TOO_LARGE;
-  int nb = grid_blocks > 0 ? grid_blocks : dev.ncu;
-  if (nb > maxb) nb = maxb;
-  const GridLayout L = grid_layout(a.m, a.n, nb, condensed, paired);
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && L.total > total_b) return LPD_ERR_OUT_OF_MEMORY;
-  void* ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, L.total, stream);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return hip_err(e);
+int lp_solve_tableau(int64_t m, int64_t ncols, const double* T0, const int64_t* basis0, const lpd_options* opt,
+                     const lpd_outputs* out, hipStream_t stream) {
+  if (!out) return LPD_ERR_NULL_POINTER;
+  if (m < 1 || ncols < m) return LPD_ERR_INVALID_ARG;
+  if (m > kMaxDim || ncols + 1 > kMaxDim) return LPD_ERR_SIZE_OVERFLOW;
+  if ((double)(m + 1) * (double)(ncols + 1) * 8.0 > 9.0e18) return LPD_ERR_SIZE_OVERFLOW;
+  if (!T0 || !basis0 || !out->x || !out->obj || !out->status) return LPD_ERR_NULL_POINTER;
+  if (out->y) return LPD_ERR_INVALID_ARG;
+  if (out->trace_cap < 0) return LPD_ERR_INVALID_ARG;
+  if (out->trace_cap > 0 && !out->trace) return LPD_ERR_NULL_POINTER;
+  std::vector<char> seen((size_t)ncols, 0);
+  for (int64_t i = 0; i < m; ++i) {
+    if (basis0[i] < 0 || basis0[i] >= ncols || seen[(size_t)basis0[i]]) return LPD_ERR_INVALID_ARG;
+    seen[(size_t)basis0[i]] = 1;
   }
-  e = launch_grid_solve(a, ws, nb, 0, stream, condensed, paired);
-  const hipError_t ef = hipFreeAsync(ws, stream);
-  if (e != hipSuccess) return hip_err(e);
-  return hip_err(ef);
+  const lpd_problem shape{m, ncols - m, nullptr, nullptr, nullptr};
+  SolveArgs a{};
+  a.m = m;
+  a.n = ncols - m;
+  a.T0 = T0;
+  a.x_count = ncols;
+  int schedule = 0, grid_blocks = 0;
+  int rc = resolve_options(&shape, opt, &a, &schedule, &grid_blocks);  // default cap 50 * ncols
+  if (rc != LPD_SUCCESS) return rc;
+  rc = bind_outputs(out, &a);
+  if (rc != LPD_SUCCESS) return rc;
+  return run_solve(a, schedule, grid_blocks, basis0, stream);
 }
 
 int lp_solve_dense(int64_t m, int64_t n, const double* A, const double* b, const double* c, double* x,

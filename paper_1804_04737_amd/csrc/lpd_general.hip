@@ -1,21 +1,28 @@
 // Two-phase solve of a general LP -- rows <=, = or >= with right-hand sides
-// of any sign -- on the pivot kernels of lp_solve_dense_ex (Section 2 states
-// the problem with equality rows; the paper's experiments start from the
-// slack basis of <= rows with b >= 0, which phase I provides in general).
+// of any sign -- on the pivot kernels (Section 2 states the problem with
+// equality rows; its Steps 1-5 start from the slack basis of <= rows with
+// b >= 0).  The textbook two-phase method, every pivot in the kernels of
+// lp_solve_tableau:
 //
-// Phase I LP, canonical form (max c1^T x1, A1 x1 <= b1, x1 >= 0, b1 >= 0):
-//   row i scaled by sigma_i = +-1 so that its right-hand side is >= 0;
-//   a row that then reads ">=" gets a surplus column (-1) and, like every
-//   "=" row, an artificial variable as its (implicit) slack: the slack basis
-//   is then feasible.  c1 = sum of the artificial rows of A1, so that
-//   c1^T x1 = sum(b1 over artificial rows) - sum(artificials): the LP is
-//   feasible iff phase I reaches that sum.
-// Phase II LP, canonical form again, whose slack basis is phase I's final
-// basis: structural columns = phase I's nonbasic non-artificial variables,
-// taken from phase I's final tableau; costs c_N - A_N^T c_B; an artificial
-// still basic (at level zero) gets a mirrored row -row <= 0 so that it stays
-// zero.  Every reduction below is one sequential sum in a fixed order, so
-// the results are reproducible bit for bit.
+//   rows      row i times sigma_i = -1 when b_i < 0, or b_i = 0 on a >= row,
+//             so that every right-hand side is >= 0;
+//   phase I   Table 1's layout [sigma A | -S | I | sigma b] (S: one surplus
+//             column per row that now reads >=; I: each row's slack, or an
+//             artificial variable on >= and = rows), objective +1 in the
+//             artificial columns with those basic columns eliminated
+//             (maximise minus the sum of the artificials); Steps 2-5;
+//   feasible  iff phase I's optimum >= -1e-9 max(1, sum of the artificial
+//             rows' right-hand sides);
+//   drive-out each artificial still basic, rows in order, leaves by a pivot
+//             on the lowest non-artificial column with |entry| > eps_p; a
+//             row without one is redundant;
+//   phase II  artificial columns and redundant rows deleted, objective row
+//             [-c | 0 | 0] with the basic columns eliminated; Steps 2-5.
+//
+// Every elimination of the objective row is Step 5's fused multiply-add, one
+// row after the other in row order, so the results are reproducible bit for
+// bit.  The host decides what depends on phase I's outcome (which rows are
+// redundant, the phase II layout) between synchronisations of the stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,100 +30,157 @@
 #include <cstring>
 #include <vector>
 
+#include "lpd_device.h"
 #include "lpdense.h"
 
 namespace lpd {
 namespace {
 
 constexpr int kTB = 256;
+constexpr int kSelectThreads = 1024;
 
-__global__ void build_phase1_kernel(int64_t m, int64_t n, int64_t n1, const double* A, const double* b,
-                                    const int8_t* sigma, const int32_t* surcol, double* A1, double* b1) {
+unsigned blocks_for(int64_t count) { return (unsigned)((count + kTB - 1) / kTB); }
+
+// Phase I constraint rows, (m x W1) of the (m+1) x W1 tableau:
+// [sigma_i A_i | -1 in row i's surplus column | 1 in column n1 + i | sigma_i b_i].
+__global__ void phase1_rows_kernel(int64_t m, int64_t n, int64_t n1, const double* A, const double* b,
+                                   const int8_t* sigma, const int32_t* surcol, double* T) {
+  const int64_t W1 = n1 + m + 1;
   const int64_t e = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (e < m * n1) {
-    const int64_t i = e / n1, j = e - i * n1;
-    double v;
-    if (j < n) v = sigma[i] > 0 ? A[i * n + j] : -A[i * n + j];
-    else v = (j - n == surcol[i]) ? -1.0 : 0.0;
-    A1[e] = v;
-  }
-  if (e < m) b1[e] = fabs(b[e]);  // sigma_i b_i >= 0 by the choice of sigma_i
+  if (e >= m * W1) return;
+  const int64_t i = e / W1, j = e - i * W1;
+  const bool neg = sigma[i] < 0;
+  double v;
+  if (j < n) v = neg ? -A[i * n + j] : A[i * n + j];
+  else if (j < n1) v = (j - n == surcol[i]) ? -1.0 : 0.0;
+  else if (j < n1 + m) v = (j - n1 == i) ? 1.0 : 0.0;
+  else v = neg ? -b[i] : b[i];
+  T[e] = v;
 }
 
-// c1_j = sum over artificial rows i (in row order) of A1[i][j].
-__global__ void artificial_row_sum_kernel(int64_t m, int64_t n1, const double* A1, const int8_t* art, double* c1) {
+// Phase I objective row: +1 in the artificial columns, then for each
+// artificial row in order (its basic column holds +1 in the objective row
+// when it comes) the elimination fma(-1, T[i][j], .) of Step 5.
+__global__ void phase1_objective_kernel(int64_t m, int64_t n1, const int8_t* art, double* T) {
+  const int64_t W1 = n1 + m + 1;
   const int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (j >= n1) return;
-  double acc = 0.0;
+  if (j >= W1) return;
+  double acc = (j >= n1 && j < n1 + m && art[j - n1]) ? 1.0 : 0.0;
   for (int64_t i = 0; i < m; ++i)
-    if (art[i]) acc = acc + A1[i * n1 + j];
-  c1[j] = acc;
+    if (art[i]) acc = __builtin_fma(-1.0, T[i * W1 + j], acc);
+  T[m * W1 + j] = acc;
 }
 
-// Phase II data from phase I's final tableau T1 ((m+1) x W1, Table 1 layout):
-// A2[i][t] = T1[src(i)][N[t]] (mirrored rows negated), b2[i] = max(rhs, +0),
-// and 0 for rows whose basic variable is an artificial.
-__global__ void build_phase2_kernel(int64_t m, int64_t W1, int64_t n2, int64_t n_extra, const double* T1,
-                                    const int32_t* N, const int32_t* extra_rows, const int8_t* zero_rhs,
-                                    double* A2, double* b2) {
-  const int64_t m2 = m + n_extra;
+// Drive-out, step 1 (one workgroup): in row `row` of the phase I tableau,
+// the lowest non-artificial column k with |T[row][k]| > eps_p.  If there is
+// one: the pivot row T[row][:] / T[row][k] (IEEE division) into prow, the
+// pivot column T[:][k] (objective row included) into pcol, and k into
+// *sel; else *sel = -1 (a redundant row).
+__global__ void __launch_bounds__(kSelectThreads)
+    driveout_select_kernel(int64_t m, int64_t n1, const int8_t* art, const double* T, int64_t row, double eps_p,
+                           double* prow, double* pcol, int32_t* sel) {
+  __shared__ Cand scratch[kSelectThreads / kWave + 1];
+  const int64_t ncols = n1 + m, W1 = ncols + 1;
+  const double* Tr = T + row * W1;
+  Cand c = cand_none();
+  for (int64_t j = threadIdx.x; j < ncols; j += blockDim.x) {
+    const bool artificial = j >= n1 && art[j - n1];
+    if (!artificial && __builtin_fabs(Tr[j]) > eps_p) cand_offer(c, 0.0, (int32_t)j, 0.0);
+  }
+  c = block_reduce(c, scratch);
+  if (c.i == kNoIndex) {
+    if (threadIdx.x == 0) *sel = -1;
+    return;
+  }
+  const int64_t k = c.i;
+  const double p = Tr[k];
+  for (int64_t j = threadIdx.x; j < W1; j += blockDim.x) prow[j] = Tr[j] / p;
+  for (int64_t i = threadIdx.x; i <= m; i += blockDim.x) pcol[i] = T[i * W1 + k];
+  if (threadIdx.x == 0) *sel = (int32_t)k;
+}
+
+// Drive-out, step 2: Steps 4-5 of that pivot over the whole tableau (the
+// pivot column was captured before any row changes).
+__global__ void driveout_apply_kernel(int64_t m, int64_t W1, double* T, int64_t row, const double* prow,
+                                      const double* pcol, const int32_t* sel) {
+  if (*sel < 0) return;
   const int64_t e = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (e < m2 * n2) {
-    const int64_t i = e / n2, t = e - i * n2;
-    const int64_t src = i < m ? i : extra_rows[i - m];
-    const double v = T1[src * W1 + N[t]];
-    A2[e] = i < m ? v : -v;
-  }
-  if (e < m2) {
-    double r = 0.0;
-    if (e < m && !zero_rhs[e]) {
-      const double t = T1[e * W1 + W1 - 1];
-      r = t > 0.0 ? t : 0.0;
-    }
-    b2[e] = r;
-  }
+  if (e >= (m + 1) * W1) return;
+  const int64_t i = e / W1, j = e - i * W1;
+  T[e] = i == row ? prow[j] : __builtin_fma(-pcol[i], prow[j], T[e]);
 }
 
-// c2_t = cN_t - sum_i cB_i A2[i][t] over the m original rows, in row order.
-__global__ void reduced_cost_kernel(int64_t m, int64_t n2, const double* A2, const double* cB, const double* cN,
-                                    double* c2) {
-  const int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (t >= n2) return;
-  double acc = 0.0;
-  for (int64_t i = 0; i < m; ++i) acc = acc + cB[i] * A2[i * n2 + t];
-  c2[t] = cN[t] - acc;
+// Phase II constraint rows: the kept rows and columns (the RHS last) of the
+// phase I tableau after the drive-out.
+__global__ void phase2_rows_kernel(int64_t m2, int64_t W2, int64_t W1, const double* T1, const int32_t* rows,
+                                   const int32_t* cols, double* T2) {
+  const int64_t e = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (e >= m2 * W2) return;
+  const int64_t i = e / W2, j = e - i * W2;
+  T2[e] = T1[(int64_t)rows[i] * W1 + cols[j]];
 }
 
-// x of the original variables: a phase II structural takes its phase II
-// value; a variable basic in phase I's basis (row i) takes row i's slack at
-// the phase II optimum, b2_i - sum_t A2[i][t] x2_t (in column order).
-__global__ void recover_kernel(int64_t m, int64_t n, int64_t n2, const double* A2, const double* b2,
-                               const double* x2, const int32_t* N, const int32_t* basis1, double* x) {
-  const int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (t < n2 && N[t] < n) x[N[t]] = x2[t];
-  if (t < m && basis1[t] < n) {
-    double acc = 0.0;
-    for (int64_t u = 0; u < n2; ++u) acc = acc + A2[t * n2 + u] * x2[u];
-    x[basis1[t]] = b2[t] - acc;
+// Phase II objective row: [-c | 0 | 0], then for each row in order with
+// f_i != 0 the elimination fma(-f_i, T2[i][j], .) of Step 5, f_i being the
+// objective-row entry of row i's basic column when row i comes: -c of a
+// basic original variable, 0 otherwise (the earlier rows are 0 in that
+// column, so it is unchanged until then).
+__global__ void phase2_objective_kernel(int64_t m2, int64_t W2, int64_t n, const double* c, const double* f,
+                                        double* T2) {
+  const int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (j >= W2) return;
+  double acc = j < n ? -c[j] : 0.0;
+  for (int64_t i = 0; i < m2; ++i)
+    if (f[i] != 0.0) acc = __builtin_fma(-f[i], T2[i * W2 + j], acc);
+  T2[m2 * W2 + j] = acc;
+}
+
+// Phase II with no constraint row left (every row redundant): Steps 2-3 on
+// the objective row alone -- optimal if no reduced cost is below -eps_d, else
+// unbounded (no row for the ratio test), or the iteration cap if it is 0.
+__global__ void __launch_bounds__(kSelectThreads)
+    no_rows_kernel(int64_t W2, const double* objrow, double eps_d, int64_t max_iter, int32_t* status) {
+  __shared__ Cand scratch[kSelectThreads / kWave + 1];
+  Cand c = cand_none();
+  for (int64_t j = threadIdx.x; j < W2; j += blockDim.x) {
+    const double v = objrow[j];
+    if (!is_finite(v)) c.flags |= kFlagNonFinite;
+    if (j < W2 - 1 && !__builtin_isnan(v)) cand_offer(c, v, (int32_t)j, 0.0);
   }
+  c = block_reduce(c, scratch);
+  if (threadIdx.x != 0) return;
+  if (c.flags & kFlagNonFinite) *status = kNumerical;
+  else if (c.v >= -eps_d) *status = kOptimal;
+  else if (max_iter == 0) *status = kIterLimit;
+  else *status = kUnbounded;
 }
 
 // obj = sum_j c_j x_j in index order (one thread: the order is the definition).
 __global__ void objective_kernel(int64_t n, const double* c, const double* x, double* obj) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   double acc = 0.0;
-#pragma unroll 8
   for (int64_t j = 0; j < n; ++j) acc = acc + c[j] * x[j];
   *obj = acc;
 }
 
-// x = the first n entries of a phase I / direct solution.
+// The n original variables' values: the first n entries of a phase's x.
 __global__ void copy_kernel(int64_t n, const double* src, double* dst) {
   const int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (j < n) dst[j] = src[j];
 }
 
-unsigned blocks_for(int64_t count) { return (unsigned)((count + kTB - 1) / kTB); }
+__global__ void zero_kernel(int64_t n, double* dst) {
+  const int64_t j = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (j < n) dst[j] = 0.0;
+}
+
+// Final status and pivot count: phase II's status and pivots plus `before`.
+__global__ void finish_kernel(const int32_t* st2, const int64_t* it2, int64_t before, int32_t* status,
+                              int64_t* iterations) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  *status = *st2;
+  if (iterations) *iterations = before + (it2 ? *it2 : 0);
+}
 
 int hip_code(hipError_t e) {
   if (e == hipSuccess) return LPD_SUCCESS;
@@ -125,7 +189,8 @@ int hip_code(hipError_t e) {
   return LPD_ERR_HIP;
 }
 
-// Stream-ordered device buffers freed together at the end.
+// Stream-ordered device buffers, freed together when the call returns (after
+// the stream has drained: the host arrays copied from live until then).
 struct Arena {
   hipStream_t s;
   std::vector<void*> ptrs;
@@ -160,177 +225,183 @@ extern "C" int lp_solve_general(int64_t m, int64_t n, const double* A, const dou
       if (sense[i] != LPD_ROW_LE && sense[i] != LPD_ROW_EQ && sense[i] != LPD_ROW_GE) return LPD_ERR_INVALID_ARG;
   lpd_options o{};
   if (opt) o = *opt;
+  if (o.max_iter < 0) o.max_iter = 50 * (m + n);  // per phase
+  if (std::isnan(o.eps_p) || std::isinf(o.eps_p)) return LPD_ERR_INVALID_ARG;
+  const double eps_p = o.eps_p > 0 ? o.eps_p : LPD_DEFAULT_EPS;
 
+  Arena ar{stream};
   std::vector<double> hb((size_t)m), hc((size_t)n);
   hipError_t e = hipMemcpyAsync(hb.data(), b, 8 * (size_t)m, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), c, 8 * (size_t)n, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_code(e);
 
-  // Row plan.
+  // Rows: sigma, the sense after scaling, surplus columns, artificials.
   std::vector<int8_t> sigma((size_t)m), art((size_t)m);
   std::vector<int32_t> surcol((size_t)m, -1);
   int32_t q = 0;
   for (int64_t i = 0; i < m; ++i) {
     const int s = sense ? sense[i] : LPD_ROW_LE;
     const double bi = hb[(size_t)i];
-    if (s == LPD_ROW_LE) {
-      const bool neg = bi < 0.0;
-      sigma[(size_t)i] = neg ? -1 : 1;
-      art[(size_t)i] = neg;
-      if (neg) surcol[(size_t)i] = q++;
-    } else if (s == LPD_ROW_GE) {
-      const bool pos = bi > 0.0;  // b <= 0: -A_i x <= -b_i is already a slack row
-      sigma[(size_t)i] = pos ? 1 : -1;
-      art[(size_t)i] = pos;
-      if (pos) surcol[(size_t)i] = q++;
-    } else {
-      sigma[(size_t)i] = bi < 0.0 ? -1 : 1;
-      art[(size_t)i] = 1;
-    }
+    const bool flip = bi < 0.0 || (bi == 0.0 && s == LPD_ROW_GE);
+    sigma[(size_t)i] = flip ? -1 : 1;
+    const int scaled = !flip ? s : (s == LPD_ROW_LE ? LPD_ROW_GE : (s == LPD_ROW_GE ? LPD_ROW_LE : LPD_ROW_EQ));
+    art[(size_t)i] = scaled != LPD_ROW_LE;
+    if (scaled == LPD_ROW_GE) surcol[(size_t)i] = q++;
   }
-  const int64_t n1 = n + q;
-  int64_t n_art = 0;
+  const int64_t n1 = n + q, ncols1 = n1 + m, W1 = ncols1 + 1;
   double sum_b_art = 0.0;
   for (int64_t i = 0; i < m; ++i)
-    if (art[(size_t)i]) {
-      ++n_art;
-      sum_b_art = sum_b_art + std::fabs(hb[(size_t)i]);
-    }
+    if (art[(size_t)i]) sum_b_art = sum_b_art + (sigma[(size_t)i] < 0 ? -hb[(size_t)i] : hb[(size_t)i]);
 
-  Arena ar{stream};
   int8_t* d_sigma = ar.get<int8_t>((size_t)m);
   int8_t* d_art = ar.get<int8_t>((size_t)m);
   int32_t* d_surcol = ar.get<int32_t>((size_t)m);
-  double* A1 = ar.get<double>((size_t)(m * n1));
-  double* b1 = ar.get<double>((size_t)m);
-  double* c1 = ar.get<double>((size_t)n1);
-  double* x1 = ar.get<double>((size_t)n1);
+  double* T1 = ar.get<double>((size_t)((m + 1) * W1));
+  double* T1f = ar.get<double>((size_t)((m + 1) * W1));
+  double* x1 = ar.get<double>((size_t)ncols1);
   double* obj1 = ar.get<double>(1);
   int32_t* st1 = ar.get<int32_t>(1);
   int64_t* it1 = ar.get<int64_t>(1);
   int64_t* basis1 = ar.get<int64_t>((size_t)m);
-  const int64_t W1 = n1 + m + 1;
-  double* T1 = n_art > 0 ? ar.get<double>((size_t)((m + 1) * W1)) : nullptr;
   if (ar.err != hipSuccess) return hip_code(ar.err);
-  (void)hipMemcpyAsync(d_sigma, sigma.data(), (size_t)m, hipMemcpyHostToDevice, stream);
-  (void)hipMemcpyAsync(d_art, art.data(), (size_t)m, hipMemcpyHostToDevice, stream);
-  (void)hipMemcpyAsync(d_surcol, surcol.data(), 4 * (size_t)m, hipMemcpyHostToDevice, stream);
-  build_phase1_kernel<<<blocks_for(std::max(m * n1, m)), kTB, 0, stream>>>(m, n, n1, A, b, d_sigma, d_surcol, A1,
-                                                                            b1);
-  if (n_art > 0) {
-    artificial_row_sum_kernel<<<blocks_for(n1), kTB, 0, stream>>>(m, n1, A1, d_art, c1);
-  } else {
-    // No artificial row: the scaled LP is canonical already; one solve with c.
-    (void)hipMemcpyAsync(c1, c, 8 * (size_t)n, hipMemcpyDeviceToDevice, stream);
-  }
+  e = hipMemcpyAsync(d_sigma, sigma.data(), (size_t)m, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_art, art.data(), (size_t)m, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_surcol, surcol.data(), 4 * (size_t)m, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_code(e);
+  phase1_rows_kernel<<<blocks_for(m * W1), kTB, 0, stream>>>(m, n, n1, A, b, d_sigma, d_surcol, T1);
+  phase1_objective_kernel<<<blocks_for(W1), kTB, 0, stream>>>(m, n1, d_art, T1);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_code(e);
 
-  lpd_problem p1{m, n1, A1, b1, c1};
+  // Phase I.
+  std::vector<int64_t> hbasis((size_t)m);
+  for (int64_t i = 0; i < m; ++i) hbasis[(size_t)i] = n1 + i;
   lpd_outputs out1{};
   out1.x = x1;
   out1.obj = obj1;
   out1.status = st1;
   out1.iterations = it1;
   out1.basis = basis1;
-  out1.tableau = T1;
-  int rc = lp_solve_dense_ex(&p1, &o, &out1, stream);
+  out1.tableau = T1f;
+  int rc = lp_solve_tableau(m, ncols1, T1, hbasis.data(), &o, &out1, stream);
   if (rc != LPD_SUCCESS) return rc;
-
   int32_t h_st1 = 0;
   int64_t h_it1 = 0;
   double h_obj1 = 0.0;
-  std::vector<int64_t> h_basis((size_t)m);
-  (void)hipMemcpyAsync(&h_st1, st1, 4, hipMemcpyDeviceToHost, stream);
-  (void)hipMemcpyAsync(&h_it1, it1, 8, hipMemcpyDeviceToHost, stream);
-  (void)hipMemcpyAsync(&h_obj1, obj1, 8, hipMemcpyDeviceToHost, stream);
-  (void)hipMemcpyAsync(h_basis.data(), basis1, 8 * (size_t)m, hipMemcpyDeviceToHost, stream);
-  e = hipStreamSynchronize(stream);
+  e = hipMemcpyAsync(&h_st1, st1, 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_it1, it1, 8, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_obj1, obj1, 8, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hbasis.data(), basis1, 8 * (size_t)m, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_code(e);
 
-  int32_t h_status = h_st1;
-  int64_t h_iters = h_it1;
-  const bool feasible =
-      h_st1 == LPD_OPTIMAL && (n_art == 0 || h_obj1 >= sum_b_art - 1e-9 * std::max(1.0, sum_b_art));
-  if (n_art == 0 || h_st1 != LPD_OPTIMAL || !feasible) {
-    // Done after one solve: the direct answer, or phase I's point with its status.
-    if (h_st1 == LPD_OPTIMAL && !feasible) h_status = LPD_INFEASIBLE;
+  const bool feasible = h_st1 == LPD_OPTIMAL && h_obj1 >= -1e-9 * std::max(1.0, sum_b_art);
+  int32_t h_status = 0;
+  if (!feasible) {
+    // No phase II: phase I's point, its status (or INFEASIBLE), c^T x.
+    h_status = h_st1 == LPD_OPTIMAL ? LPD_INFEASIBLE : h_st1;
     copy_kernel<<<blocks_for(n), kTB, 0, stream>>>(n, x1, x);
-  } else {
-    // Phase II layout from phase I's basis.
-    std::vector<int8_t> basic((size_t)(n1 + m), 0);
-    for (int64_t i = 0; i < m; ++i) basic[(size_t)h_basis[(size_t)i]] = 1;
-    std::vector<int32_t> N, extra;
-    std::vector<int8_t> zero_rhs((size_t)m, 0);
-    for (int64_t v = 0; v < n1 + m; ++v) {
-      const bool is_art = v >= n1 && art[(size_t)(v - n1)];
-      if (!basic[(size_t)v] && !is_art) N.push_back((int32_t)v);
-    }
-    std::vector<double> cB((size_t)m), cN(N.size());
-    std::vector<int32_t> b1v((size_t)m);
-    for (int64_t i = 0; i < m; ++i) {
-      const int64_t v = h_basis[(size_t)i];
-      b1v[(size_t)i] = (int32_t)v;
-      cB[(size_t)i] = v < n ? hc[(size_t)v] : 0.0;
-      if (v >= n1 && art[(size_t)(v - n1)]) {  // artificial left basic, at level zero
-        extra.push_back((int32_t)i);
-        zero_rhs[(size_t)i] = 1;
-      }
-    }
-    for (size_t t = 0; t < N.size(); ++t) cN[t] = N[t] < n ? hc[(size_t)N[t]] : 0.0;
-    const int64_t n2 = (int64_t)N.size(), m2 = m + (int64_t)extra.size();
-
-    int32_t* d_N = ar.get<int32_t>(N.size() + 1);
-    int32_t* d_extra = ar.get<int32_t>(extra.size() + 1);
-    int8_t* d_zero = ar.get<int8_t>((size_t)m);
-    int32_t* d_b1v = ar.get<int32_t>((size_t)m);
-    double* d_cB = ar.get<double>((size_t)m);
-    double* d_cN = ar.get<double>(N.size() + 1);
-    double* A2 = ar.get<double>((size_t)(m2 * std::max<int64_t>(n2, 1)));
-    double* b2 = ar.get<double>((size_t)m2);
-    double* c2 = ar.get<double>((size_t)std::max<int64_t>(n2, 1));
-    double* x2 = ar.get<double>((size_t)std::max<int64_t>(n2, 1));
-    double* obj2 = ar.get<double>(1);
-    int32_t* st2 = ar.get<int32_t>(1);
-    int64_t* it2 = ar.get<int64_t>(1);
-    if (ar.err != hipSuccess) return hip_code(ar.err);
-    if (n2) (void)hipMemcpyAsync(d_N, N.data(), 4 * N.size(), hipMemcpyHostToDevice, stream);
-    if (!extra.empty()) (void)hipMemcpyAsync(d_extra, extra.data(), 4 * extra.size(), hipMemcpyHostToDevice, stream);
-    (void)hipMemcpyAsync(d_zero, zero_rhs.data(), (size_t)m, hipMemcpyHostToDevice, stream);
-    (void)hipMemcpyAsync(d_b1v, b1v.data(), 4 * (size_t)m, hipMemcpyHostToDevice, stream);
-    (void)hipMemcpyAsync(d_cB, cB.data(), 8 * (size_t)m, hipMemcpyHostToDevice, stream);
-    if (n2) (void)hipMemcpyAsync(d_cN, cN.data(), 8 * N.size(), hipMemcpyHostToDevice, stream);
-    build_phase2_kernel<<<blocks_for(std::max(m2 * n2, m2)), kTB, 0, stream>>>(
-        m, W1, n2, (int64_t)extra.size(), T1, d_N, d_extra, d_zero, A2, b2);
-    int32_t h_st2 = LPD_OPTIMAL;
-    int64_t h_it2 = 0;
-    if (n2 > 0) {
-      reduced_cost_kernel<<<blocks_for(n2), kTB, 0, stream>>>(m, n2, A2, d_cB, d_cN, c2);
-      e = hipGetLastError();
-      if (e != hipSuccess) return hip_code(e);
-      lpd_problem p2{m2, n2, A2, b2, c2};
-      lpd_outputs out2{};
-      out2.x = x2;
-      out2.obj = obj2;
-      out2.status = st2;
-      out2.iterations = it2;
-      rc = lp_solve_dense_ex(&p2, &o, &out2, stream);
-      if (rc != LPD_SUCCESS) return rc;
-      (void)hipMemcpyAsync(&h_st2, st2, 4, hipMemcpyDeviceToHost, stream);
-      (void)hipMemcpyAsync(&h_it2, it2, 8, hipMemcpyDeviceToHost, stream);
-    }
-    recover_kernel<<<blocks_for(std::max(n2, m)), kTB, 0, stream>>>(m, n, n2, A2, b2, x2, d_N, d_b1v, x);
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_code(e);
-    h_status = h_st2;
-    h_iters = h_it1 + h_it2;
+    objective_kernel<<<1, 1, 0, stream>>>(n, c, x, obj);
+    e = hipMemcpyAsync(status, &h_status, 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && iterations) e = hipMemcpyAsync(iterations, &h_it1, 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host sources outlive the copies
+    return hip_code(e);
   }
-  objective_kernel<<<1, 1, 0, stream>>>(n, c, x, obj);
-  (void)hipMemcpyAsync(status, &h_status, 4, hipMemcpyHostToDevice, stream);
-  if (iterations) (void)hipMemcpyAsync(iterations, &h_iters, 8, hipMemcpyHostToDevice, stream);
+
+  // Drive-out of the artificial variables still basic, rows in order.
+  auto is_art_col = [&](int64_t j) { return j >= n1 && art[(size_t)(j - n1)]; };
+  std::vector<int64_t> cand_rows;
+  for (int64_t i = 0; i < m; ++i)
+    if (is_art_col(hbasis[(size_t)i])) cand_rows.push_back(i);
+  std::vector<int32_t> sel(cand_rows.size() + 1, -1);
+  if (!cand_rows.empty()) {
+    double* prow = ar.get<double>((size_t)W1);
+    double* pcol = ar.get<double>((size_t)(m + 1));
+    int32_t* d_sel = ar.get<int32_t>(cand_rows.size());
+    if (ar.err != hipSuccess) return hip_code(ar.err);
+    for (size_t t = 0; t < cand_rows.size(); ++t) {
+      driveout_select_kernel<<<1, kSelectThreads, 0, stream>>>(m, n1, d_art, T1f, cand_rows[t], eps_p, prow, pcol,
+                                                               d_sel + t);
+      driveout_apply_kernel<<<blocks_for((m + 1) * W1), kTB, 0, stream>>>(m, W1, T1f, cand_rows[t], prow, pcol,
+                                                                          d_sel + t);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(sel.data(), d_sel, 4 * cand_rows.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_code(e);
+  }
+  int64_t n_drive = 0;
+  std::vector<char> redundant((size_t)m, 0);
+  for (size_t t = 0; t < cand_rows.size(); ++t) {
+    if (sel[t] >= 0) {
+      hbasis[(size_t)cand_rows[t]] = sel[t];
+      ++n_drive;
+    } else {
+      redundant[(size_t)cand_rows[t]] = 1;
+    }
+  }
+
+  // Phase II layout: kept rows and (non-artificial) columns, the RHS last.
+  std::vector<int32_t> rows, cols, where((size_t)ncols1, -1);
+  for (int64_t i = 0; i < m; ++i)
+    if (!redundant[(size_t)i]) rows.push_back((int32_t)i);
+  for (int64_t j = 0; j < ncols1; ++j)
+    if (!is_art_col(j)) {
+      where[(size_t)j] = (int32_t)cols.size();
+      cols.push_back((int32_t)j);
+    }
+  cols.push_back((int32_t)ncols1);
+  const int64_t m2 = (int64_t)rows.size(), W2 = (int64_t)cols.size(), ncols2 = W2 - 1;
+  std::vector<int64_t> basis2((size_t)m2);
+  std::vector<double> f((size_t)std::max<int64_t>(m2, 1), 0.0);
+  for (int64_t r = 0; r < m2; ++r) {
+    const int64_t v = hbasis[(size_t)rows[(size_t)r]];
+    basis2[(size_t)r] = where[(size_t)v];
+    f[(size_t)r] = v < n ? -hc[(size_t)v] : 0.0;
+  }
+  int32_t* d_rows = ar.get<int32_t>(rows.size() + 1);
+  int32_t* d_cols = ar.get<int32_t>(cols.size());
+  double* d_f = ar.get<double>(f.size());
+  double* T2 = ar.get<double>((size_t)((m2 + 1) * W2));
+  double* x2 = ar.get<double>((size_t)ncols2);
+  double* obj2 = ar.get<double>(1);
+  int32_t* st2 = ar.get<int32_t>(1);
+  int64_t* it2 = ar.get<int64_t>(1);
+  if (ar.err != hipSuccess) return hip_code(ar.err);
+  e = hipSuccess;
+  if (m2 > 0) e = hipMemcpyAsync(d_rows, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_cols, cols.data(), 4 * cols.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_f, f.data(), 8 * f.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_code(e);
+  if (m2 > 0) phase2_rows_kernel<<<blocks_for(m2 * W2), kTB, 0, stream>>>(m2, W2, W1, T1f, d_rows, d_cols, T2);
+  phase2_objective_kernel<<<blocks_for(W2), kTB, 0, stream>>>(m2, W2, n, c, d_f, T2);
   e = hipGetLastError();
-  const hipError_t es = hipStreamSynchronize(stream);  // host sources above must outlive the copies
-  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return hip_code(e);
+
+  // Phase II.
+  if (m2 == 0) {
+    no_rows_kernel<<<1, kSelectThreads, 0, stream>>>(W2, T2, o.eps_d > 0 ? o.eps_d : LPD_DEFAULT_EPS, o.max_iter,
+                                                     st2);
+    zero_kernel<<<blocks_for(n), kTB, 0, stream>>>(n, x);
+    e = hipMemcpyAsync(obj, T2 + (W2 - 1), 8, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_code(e);
+    finish_kernel<<<1, 1, 0, stream>>>(st2, nullptr, h_it1 + n_drive, status, iterations);
+  } else {
+    lpd_outputs out2{};
+    out2.x = x2;
+    out2.obj = obj2;
+    out2.status = st2;
+    out2.iterations = it2;
+    rc = lp_solve_tableau(m2, ncols2, T2, basis2.data(), &o, &out2, stream);
+    if (rc != LPD_SUCCESS) return rc;
+    copy_kernel<<<blocks_for(n), kTB, 0, stream>>>(n, x2, x);  // the first n columns are x's
+    e = hipMemcpyAsync(obj, obj2, 8, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_code(e);
+    finish_kernel<<<1, 1, 0, stream>>>(st2, it2, h_it1 + n_drive, status, iterations);
+  }
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   return hip_code(e);
 }

@@ -41,6 +41,20 @@ struct SolveArgs {
   // budget is ignored when state is null.
   SolveState* state;
   int64_t pivot_budget;
+  // Start from a given basic tableau instead of building Table 1 from A, b,
+  // c (T0 null: Table 1).  With ncols = n + m variable columns, T0 is
+  // (m+1) x (ncols+1) row-major, RHS last, objective row last; basis0[i] is
+  // the variable of row i and pos0[j] the row of variable j (-1 if
+  // nonbasic).  Condensed tableau: lab0[c] (n + 1 entries, the last unused)
+  // is the variable held in stored column c, the nonbasic variables in
+  // increasing order, and colof0[j] the stored column of variable j (-1 if
+  // basic).
+  const double* T0;
+  const int32_t* basis0;
+  const int32_t* pos0;
+  const int32_t* lab0;
+  const int32_t* colof0;
+  int64_t x_count;  // entries of x written by the read-out (0: n)
 };
 
 // Reduction-barrier slot: one per workgroup and per epoch parity, 128 B apart.

@@ -311,16 +311,31 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     kprev = a.state->kprev;
     fpar = (int32_t)(iter & 1);
   } else {
-    // ---------------- Step 1: initial tableau (Table 1) ----------------
+    // ---------------- Step 1: initial tableau ----------------
+    // Table 1 from A, b, c, or (T0) a given basic tableau copied as it is
+    // (condensed: its nonbasic columns), with its right-hand side unchecked.
     int32_t flags = 0;
+    const double* const T0 = a.T0;
+    const int64_t W0 = (int64_t)ncols + 1;  // row length of T0
     {
       int32_t i = i_start, v = v_start;
       while (i < m) {
         const int32_t j0 = 2 * v, j1 = 2 * v + 1;
-        const double* Ai = a.A + (int64_t)i * n;
         dbl2 t;
-        t.x = j0 < n ? Ai[j0] : (!CD && j0 == n + i ? 1.0 : 0.0);
-        t.y = j1 < n ? Ai[j1] : (!CD && j1 == n + i ? 1.0 : 0.0);
+        if (T0) {
+          const double* Ti = T0 + (int64_t)i * W0;
+          if (CD) {
+            t.x = j0 < n ? Ti[a.lab0[j0]] : 0.0;
+            t.y = j1 < n ? Ti[a.lab0[j1]] : 0.0;
+          } else {
+            t.x = j0 < ncols ? Ti[j0] : 0.0;
+            t.y = j1 < ncols ? Ti[j1] : 0.0;
+          }
+        } else {
+          const double* Ai = a.A + (int64_t)i * n;
+          t.x = j0 < n ? Ai[j0] : (!CD && j0 == n + i ? 1.0 : 0.0);
+          t.y = j1 < n ? Ai[j1] : (!CD && j1 == n + i ? 1.0 : 0.0);
+        }
         if (!is_finite(t.x) || !is_finite(t.y)) flags |= kFlagNonFinite;
         st_stream(reinterpret_cast<dbl2*>(w.T + (int64_t)i * ld) + v, t);
         v += step_r;
@@ -331,14 +346,24 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     for (int64_t v = gid; v < vw; v += G) {
       const int64_t j0 = 2 * v, j1 = 2 * v + 1;
       dbl2 o;
-      o.x = j0 < n ? -a.c[j0] : 0.0;
-      o.y = j1 < n ? -a.c[j1] : 0.0;
+      if (T0) {
+        const double* Tobj = T0 + (int64_t)m * W0;
+        o.x = j0 < sc ? Tobj[CD ? a.lab0[j0] : j0] : 0.0;
+        o.y = j1 < sc ? Tobj[CD ? a.lab0[j1] : j1] : 0.0;
+      } else {
+        o.x = j0 < n ? -a.c[j0] : 0.0;
+        o.y = j1 < n ? -a.c[j1] : 0.0;
+      }
       if (!is_finite(o.x) || !is_finite(o.y)) flags |= kFlagNonFinite;
       reinterpret_cast<dbl2*>(w.obj[0])[v] = o;
     }
     for (int64_t i = gid; i <= m; i += G) {
       double bi = 0.0;
-      if (i < m) {
+      if (T0) {
+        bi = T0[i * W0 + ncols];
+        if (!is_finite(bi)) flags |= kFlagNonFinite;
+        if (i < m) w.basis[i] = a.basis0[i];
+      } else if (i < m) {
         bi = a.b[i];
         if (!is_finite(bi)) flags |= kFlagNonFinite;
         if (bi < 0.0) flags |= kFlagNegativeB;
@@ -347,10 +372,18 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       w.rhs[0][i] = bi;
     }
     for (int64_t j = gid; j < ncols; j += G) {
-      w.pos[j] = j < n ? -1 : (int32_t)(j - n);
-      if (CD) {
-        w.col_of[j] = j < n ? (int32_t)j : -1;
-        if (j < n) w.lab[j] = (int32_t)j;
+      if (T0) {
+        w.pos[j] = a.pos0[j];
+        if (CD) {
+          w.col_of[j] = a.colof0[j];
+          if (j < n) w.lab[j] = a.lab0[j];
+        }
+      } else {
+        w.pos[j] = j < n ? -1 : (int32_t)(j - n);
+        if (CD) {
+          w.col_of[j] = j < n ? (int32_t)j : -1;
+          if (j < n) w.lab[j] = (int32_t)j;
+        }
       }
     }
 
@@ -381,16 +414,23 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       const dbl2* o = reinterpret_cast<const dbl2*>(w.obj[0]);
       for (int32_t v = tid; v < vw; v += NT) {
         const dbl2 ov = o[v];
-        // Stored column c holds variable c before the first pivot.
-        price_offer(pc, ov.x, 2 * (int64_t)v, sc);
-        price_offer(pc, ov.y, 2 * (int64_t)v + 1, sc);
+        if constexpr (CD) {
+          // Ties go to the lowest variable label (stored column c holds
+          // variable c in Table 1).
+          const int2 lb = *reinterpret_cast<const int2*>(w.lab + 2 * v);
+          price_offer_cd(pc, ov.x, lb.x, 2 * v, sc);
+          price_offer_cd(pc, ov.y, lb.y, 2 * v + 1, sc);
+        } else {
+          price_offer(pc, ov.x, 2 * (int64_t)v, sc);
+          price_offer(pc, ov.y, 2 * (int64_t)v + 1, sc);
+        }
       }
       pc = block_reduce(pc, scratch);
       if (pc.flags & kFlagNonFinite) status = kNumerical;
       else if (pc.v >= -a.eps_d) status = kOptimal;
       else if (a.max_iter == 0) status = kIterLimit;
       k = pc.i;
-      kc = pc.i;
+      kc = CD ? (int32_t)pc.aux : pc.i;
       g = pc.v;
     }
     // ---------------- Step 3 on the initial tableau ----------------
@@ -1159,7 +1199,8 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const double* rhs_f = w.rhs[fpar];
   const double* obj_f = w.obj[fpar];
   const double* pr_last = w.pr[fpar ^ 1];  // normalised row of the last pivot
-  for (int64_t j = gid; j < n; j += G) {
+  const int64_t nx = a.x_count > 0 ? a.x_count : n;
+  for (int64_t j = gid; j < nx; j += G) {
     const int32_t r = w.pos[j];
     a.x[j] = r >= 0 ? rhs_f[r] : 0.0;
   }

@@ -76,13 +76,16 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   Cand* scratch = reinterpret_cast<Cand*>(smem + L.off_scratch);
   const int tid = Grp::rank(), lane = tid & (kWave - 1), wave = tid / kWave, nw = NT / kWave;
 
-  // Step 1: Table 1 layout, RHS in column W-1, objective row last.
+  // Step 1: Table 1 layout, RHS in column W-1, objective row last; or (T0)
+  // a given basic tableau of that layout, its right-hand side unchecked.
   int32_t flags = 0;
   for (int32_t i = wave; i < R; i += nw) {
     double* Ti = T + (size_t)i * W;
     for (int32_t j = lane; j < W; j += kWave) {
       double v;
-      if (i < m) {
+      if (a.T0) {
+        v = a.T0[(int64_t)i * W + j];
+      } else if (i < m) {
         if (j < n) v = a.A[(int64_t)i * n + j];
         else if (j < ncols) v = (j - n == i) ? 1.0 : 0.0;
         else {
@@ -96,7 +99,7 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
       Ti[j] = v;
     }
   }
-  for (int32_t i = tid; i < m; i += NT) basis[i] = n + i;
+  for (int32_t i = tid; i < m; i += NT) basis[i] = a.T0 ? a.basis0[i] : n + i;
   Cand fc = cand_none();
   fc.flags = flags;
   fc = Grp::reduce(fc, scratch);
@@ -162,11 +165,12 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   }
 
   // Read-out: x from the basic rows' RHS, objective value, duals.
-  for (int32_t j = tid; j < n; j += NT) a.x[j] = 0.0;
+  const int32_t nx = a.x_count > 0 ? (int32_t)a.x_count : n;
+  for (int32_t j = tid; j < nx; j += NT) a.x[j] = 0.0;
   Grp::order_global();
   for (int32_t i = tid; i < m; i += NT) {
     const int32_t bv = basis[i];
-    if (bv < n) a.x[bv] = T[(size_t)i * W + W - 1];
+    if (bv < nx) a.x[bv] = T[(size_t)i * W + W - 1];
     if (a.y) a.y[i] = Tm[n + i];
     if (a.basis_out) a.basis_out[i] = bv;
   }

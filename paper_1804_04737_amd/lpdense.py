@@ -22,7 +22,7 @@ SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED, SCHED_GRID_PAIRED
 SCHED_GRID_CONDENSED_PAIRED = 5
 
 # Exported symbols, as declared in include/lpdense.h.
-EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_batch", "lp_solve_general", "lpd_server_create",
+EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_tableau", "lp_solve_batch", "lp_solve_general", "lpd_server_create",
            "lpd_server_submit", "lpd_server_poll", "lpd_server_get_stats", "lpd_server_destroy",
            "lpd_workspace_bytes", "lpd_error_string", "lpd_status_string", "lpd_version")
 
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.lp_solve_dense_ex.restype = ctypes.c_int
     lib.lp_solve_dense_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                       ctypes.POINTER(Outputs), _P]
+    lib.lp_solve_tableau.restype = ctypes.c_int
+    lib.lp_solve_tableau.argtypes = [_I64, _I64, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _P]
     lib.lp_solve_batch.restype = ctypes.c_int
     lib.lp_solve_batch.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                    ctypes.POINTER(BatchOptions), _P]
@@ -224,6 +226,47 @@ def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter:
                                   _stream_handle(stream))
     if rc != 0:
         raise LpdError(rc, "lp_solve_dense_ex")
+    return res
+
+
+def solve_tableau(T0, basis0, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
+                  schedule: int = SCHED_AUTO, grid_blocks: int = 0, trace_cap: int = 0,
+                  want_basis: bool = False, want_tableau: bool = False, stream=None) -> DenseResult:
+    """lp_solve_tableau: Steps 2-5 from the basic tableau T0 (a (m+1) x
+    (ncols+1) device tensor, RHS last, objective row last) whose row i has
+    basic variable basis0[i] (host sequence of m column indices).  Outputs
+    are fresh device tensors; x has ncols entries (asynchronous)."""
+    import numpy as np
+    import torch
+    if T0.dim() != 2:
+        raise ValueError("T0 must be a matrix")
+    m, ncols = T0.shape[0] - 1, T0.shape[1] - 1
+    _check_dev("T0", T0, torch.float64, (m + 1) * (ncols + 1))
+    b0 = np.ascontiguousarray(np.asarray(basis0, dtype=np.int64))
+    if b0.shape != (m,):
+        raise ValueError("basis0 must have one entry per constraint row")
+    dev = T0.device
+    f64, i32, i64 = torch.float64, torch.int32, torch.int64
+    res = DenseResult(
+        x=torch.empty(ncols, dtype=f64, device=dev),
+        obj=torch.empty(1, dtype=f64, device=dev),
+        status=torch.empty(1, dtype=i32, device=dev),
+        y=None,
+        iterations=torch.empty(1, dtype=i64, device=dev),
+        trace=torch.empty((max(trace_cap, 0), 2), dtype=i32, device=dev) if trace_cap > 0 else None,
+        basis=torch.empty(m, dtype=i64, device=dev) if want_basis else None,
+        tableau=torch.empty((m + 1, ncols + 1), dtype=f64, device=dev) if want_tableau else None,
+    )
+    opts = Options(float(eps_d), float(eps_p), int(max_iter), int(schedule), int(grid_blocks))
+    outs = Outputs(res.x.data_ptr(), res.obj.data_ptr(), res.status.data_ptr(), None,
+                   res.iterations.data_ptr(),
+                   res.trace.data_ptr() if res.trace is not None else None, int(max(trace_cap, 0)),
+                   res.basis.data_ptr() if res.basis is not None else None,
+                   res.tableau.data_ptr() if res.tableau is not None else None, None, 0)
+    rc = load().lp_solve_tableau(m, ncols, T0.data_ptr(), b0.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(opts), ctypes.byref(outs), _stream_handle(stream))
+    if rc != 0:
+        raise LpdError(rc, "lp_solve_tableau")
     return res
 
 

@@ -68,6 +68,27 @@ def test_host_validation_without_device():
         assert lib.lp_solve_dense_ex(ctypes.byref(p), ctypes.byref(opts), ctypes.byref(o), None) == -1
 
 
+def test_tableau_host_validation_without_device():
+    """lp_solve_tableau rejects bad arguments on the host, before any HIP
+    call (no GPU here)."""
+    import numpy as np
+    lib = lpdense.load()
+    d = 0x1000
+    o = lpdense.Outputs(d, d, d, None, None, None, 0, None, None, None, 0)
+    basis = np.array([0, 1], dtype=np.int64)
+    bp = basis.ctypes.data_as(ctypes.c_void_p)
+    f = lib.lp_solve_tableau
+    assert f(0, 3, ctypes.c_void_p(d), bp, None, ctypes.byref(o), None) == -1   # m < 1
+    assert f(3, 2, ctypes.c_void_p(d), bp, None, ctypes.byref(o), None) == -1   # ncols < m
+    assert f(2, 4, None, bp, None, ctypes.byref(o), None) == -2                  # no tableau
+    assert f(2, 4, ctypes.c_void_p(d), None, None, ctypes.byref(o), None) == -2  # no basis
+    for bad in ([0, 0], [0, 4], [-1, 1]):
+        bb = np.array(bad, dtype=np.int64)
+        assert f(2, 4, ctypes.c_void_p(d), bb.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(o), None) == -1
+    oy = lpdense.Outputs(d, d, d, d, None, None, 0, None, None, None, 0)      # y is not an output here
+    assert f(2, 4, ctypes.c_void_p(d), bp, None, ctypes.byref(oy), None) == -1
+
+
 def test_batch_host_validation_without_device():
     lib = lpdense.load()
     import numpy as np
