@@ -173,6 +173,26 @@ typedef struct lpd_outputs {
 int lp_solve_dense_ex(const lpd_problem *prob, const lpd_options *opt, const lpd_outputs *out,
                       hipStream_t stream);
 
+/*
+ * lp_solve_dense_noalloc: lp_solve_dense_ex for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results (bitwise), errors and
+ * stream ordering as lp_solve_dense_ex, but no allocation of any kind: the
+ * grid schedules take their workspace from a fixed 128 MiB device array
+ * that the library holds on every device it runs on until the process ends
+ * (looked up on the first call on each device).  A problem whose workspace
+ * (lpd_workspace_bytes, or the paired schedules' larger one) exceeds 128 MiB
+ * returns LPD_ERR_TOO_LARGE with nothing enqueued: about m = n = 2,800 on the
+ * full tableau, m = n = 4,000 on the condensed one.  LPs whose tableau fits
+ * in LDS need no workspace and have no size limit beyond lp_solve_dense_ex's.
+ * Every call on a device uses the same array: calls whose work overlaps on
+ * one device (different streams, or other host threads) race and corrupt
+ * each other's results; serialise them, e.g. on one stream.  The array
+ * keeps the last call's contents; the kernels reset what must start at zero.
+ */
+int lp_solve_dense_noalloc(const lpd_problem *prob, const lpd_options *opt, const lpd_outputs *out,
+                           hipStream_t stream);
+
 /* Options of a batched solve (host struct; zero-initialise for defaults). */
 typedef struct lpd_batch_options {
     double eps_d;            /* as lpd_options, for every LP (<= 0: 1e-9) */

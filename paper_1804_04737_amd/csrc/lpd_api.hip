@@ -18,6 +18,14 @@
 #include "lpd_kernels.h"
 #include "lpdense.h"
 
+// Workspace of lp_solve_dense_noalloc: a file-scope device array, one copy
+// per device, held until the process ends.  In host code its name is not a
+// device address: the library passes kernels the address that
+// hipGetSymbolAddress returns for the current device.  Every call on a device
+// shares that device's copy.
+constexpr uint64_t kScratchMax = 128ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchMax];
+
 namespace lpd {
 namespace {
 
@@ -193,6 +201,23 @@ int run_batch(BatchPlan& P, const std::vector<int32_t>& idx, const int64_t* m, c
 }
 
 
+// Device address of `scratch` on each device (null until looked up).
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (null if the lookup failed).
+void* scratch_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[dev] = ptr;
+    else (void)hipGetLastError();
+  });
+  return g_scratch_ptr[dev];
+}
+
 // Index arrays of a start from a given basic tableau, laid out as
 // [basis (m) | pos (ncols) | lab (n + 1) | colof (ncols)] (lab and colof for
 // the condensed tableau only, n = ncols - m), built on the host and copied
@@ -247,9 +272,12 @@ hipError_t upload_start_index(StartIndex* si, int32_t* dev, SolveArgs& a, bool c
 }
 
 // Runs the solve described by `a` (inputs, options and outputs set) on
-// `schedule`, its workspace allocated stream-ordered on `stream`.  `basis0`
-// (host, m entries) starts from the tableau a.T0 instead of Table 1.
-int run_solve(SolveArgs& a, int schedule, int grid_blocks, const int64_t* basis0, hipStream_t stream) {
+// `schedule`.  The workspace is allocated stream-ordered on `stream`, or
+// (noalloc) taken from `scratch` (kScratchMax bytes, no allocation at all:
+// sizes beyond it are rejected).  `basis0` (host, m entries) starts from the
+// tableau a.T0 instead of Table 1.
+int run_solve(SolveArgs& a, int schedule, int grid_blocks, bool noalloc, const int64_t* basis0,
+              hipStream_t stream) {
   DeviceInfo dev;
   int rc = device_info(&dev);
   if (rc != LPD_SUCCESS) return rc;
@@ -282,6 +310,13 @@ int run_solve(SolveArgs& a, int schedule, int grid_blocks, const int64_t* basis0
   int nb = grid_blocks > 0 ? grid_blocks : dev.ncu;
   if (nb > maxb) nb = maxb;
   const GridLayout L = grid_layout(a.m, a.n, nb, condensed, paired);
+  if (noalloc) {
+    if (basis0) return LPD_ERR_INVALID_ARG;
+    if (L.total > kScratchMax) return LPD_ERR_TOO_LARGE;
+    void* ws = scratch_ptr();
+    if (!ws) return LPD_ERR_HIP;
+    return hip_err(launch_grid_solve(a, ws, nb, 0, stream, condensed, paired));
+  }
   StartIndex* si = basis0 ? start_index(a.m, ncols, basis0, condensed) : nullptr;
   const uint64_t meta_bytes = si ? (uint64_t)si->v.size() * 4 : 0;
   size_t free_b = 0, total_b = 0;
@@ -322,8 +357,9 @@ int bind_outputs(const lpd_outputs* out, SolveArgs* a) {
   return LPD_SUCCESS;
 }
 
-// lp_solve_dense_ex.
-int solve_dense(const lpd_problem* prob, const lpd_options* opt, const lpd_outputs* out, hipStream_t stream) {
+// lp_solve_dense_ex (noalloc: lp_solve_dense_noalloc).
+int solve_dense(const lpd_problem* prob, const lpd_options* opt, const lpd_outputs* out, hipStream_t stream,
+                bool noalloc) {
   int rc = validate(prob, out);
   if (rc != LPD_SUCCESS) return rc;
   SolveArgs a{};
@@ -337,7 +373,7 @@ int solve_dense(const lpd_problem* prob, const lpd_options* opt, const lpd_outpu
   if (rc != LPD_SUCCESS) return rc;
   rc = bind_outputs(out, &a);
   if (rc != LPD_SUCCESS) return rc;
-  return run_solve(a, schedule, grid_blocks, nullptr, stream);
+  return run_solve(a, schedule, grid_blocks, noalloc, nullptr, stream);
 }
 
 }  // namespace
@@ -359,7 +395,12 @@ extern "C" {
 
 int lp_solve_dense_ex(const lpd_problem* prob, const lpd_options* opt, const lpd_outputs* out,
                       hipStream_t stream) {
-  return solve_dense(prob, opt, out, stream);
+  return solve_dense(prob, opt, out, stream, false);
+}
+
+int lp_solve_dense_noalloc(const lpd_problem* prob, const lpd_options* opt, const lpd_outputs* out,
+                           hipStream_t stream) {
+  return solve_dense(prob, opt, out, stream, true);
 }
 
 int lp_solve_tableau(int64_t m, int64_t ncols, const double* T0, const int64_t* basis0, const lpd_options* opt,
@@ -388,7 +429,7 @@ int lp_solve_tableau(int64_t m, int64_t ncols, const double* T0, const int64_t* 
   if (rc != LPD_SUCCESS) return rc;
   rc = bind_outputs(out, &a);
   if (rc != LPD_SUCCESS) return rc;
-  return run_solve(a, schedule, grid_blocks, basis0, stream);
+  return run_solve(a, schedule, grid_blocks, false, basis0, stream);
 }
 
 int lp_solve_dense(int64_t m, int64_t n, const double* A, const double* b, const double* c, double* x,

@@ -22,7 +22,7 @@ SCHED_AUTO, SCHED_WORKGROUP, SCHED_GRID, SCHED_GRID_CONDENSED, SCHED_GRID_PAIRED
 SCHED_GRID_CONDENSED_PAIRED = 5
 
 # Exported symbols, as declared in include/lpdense.h.
-EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_tableau", "lp_solve_batch", "lp_solve_general", "lpd_server_create",
+EXPORTS = ("lp_solve_dense", "lp_solve_dense_ex", "lp_solve_dense_noalloc", "lp_solve_tableau", "lp_solve_batch", "lp_solve_general", "lpd_server_create",
            "lpd_server_submit", "lpd_server_poll", "lpd_server_get_stats", "lpd_server_destroy",
            "lpd_workspace_bytes", "lpd_error_string", "lpd_status_string", "lpd_version")
 
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.lp_solve_dense_ex.restype = ctypes.c_int
     lib.lp_solve_dense_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                       ctypes.POINTER(Outputs), _P]
+    lib.lp_solve_dense_noalloc.restype = ctypes.c_int
+    lib.lp_solve_dense_noalloc.argtypes = lib.lp_solve_dense_ex.argtypes
     lib.lp_solve_tableau.restype = ctypes.c_int
     lib.lp_solve_tableau.argtypes = [_I64, _I64, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _P]
     lib.lp_solve_batch.restype = ctypes.c_int
@@ -190,9 +192,11 @@ class DenseResult:
 def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
                    schedule: int = SCHED_AUTO, grid_blocks: int = 0, want_y: bool = True,
                    trace_cap: int = 0, want_basis: bool = False, want_tableau: bool = False,
-                   phase_cap: int = 0, stream=None) -> DenseResult:
+                   phase_cap: int = 0, stream=None, noalloc: bool = False) -> DenseResult:
     """lp_solve_dense_ex on device tensors; outputs are freshly allocated
-    device tensors (asynchronous: synchronise the stream before reading)."""
+    device tensors (asynchronous: synchronise the stream before reading).
+    noalloc=True calls lp_solve_dense_noalloc instead (the library's fixed
+    workspace, no device allocation inside the call)."""
     import torch
     m, n = A.shape
     _check_dev("A", A, torch.float64, m * n)
@@ -222,10 +226,10 @@ def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter:
                    res.tableau.data_ptr() if res.tableau is not None else None,
                    res.phase_ticks.data_ptr() if res.phase_ticks is not None else None,
                    int(max(phase_cap, 0)))
-    rc = load().lp_solve_dense_ex(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(outs),
-                                  _stream_handle(stream))
+    fn = load().lp_solve_dense_noalloc if noalloc else load().lp_solve_dense_ex
+    rc = fn(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(outs), _stream_handle(stream))
     if rc != 0:
-        raise LpdError(rc, "lp_solve_dense_ex")
+        raise LpdError(rc, "lp_solve_dense_noalloc" if noalloc else "lp_solve_dense_ex")
     return res
 
 

@@ -68,9 +68,9 @@ def test_host_validation_without_device():
         assert lib.lp_solve_dense_ex(ctypes.byref(p), ctypes.byref(opts), ctypes.byref(o), None) == -1
 
 
-def test_tableau_host_validation_without_device():
-    """lp_solve_tableau rejects bad arguments on the host, before any HIP
-    call (no GPU here)."""
+def test_tableau_and_noalloc_host_validation_without_device():
+    """lp_solve_tableau and lp_solve_dense_noalloc reject bad arguments on
+    the host, before any HIP call (no GPU here)."""
     import numpy as np
     lib = lpdense.load()
     d = 0x1000
@@ -87,6 +87,9 @@ def test_tableau_host_validation_without_device():
         assert f(2, 4, ctypes.c_void_p(d), bb.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(o), None) == -1
     oy = lpdense.Outputs(d, d, d, d, None, None, 0, None, None, None, 0)      # y is not an output here
     assert f(2, 4, ctypes.c_void_p(d), bp, None, ctypes.byref(oy), None) == -1
+    assert lib.lp_solve_dense_noalloc(None, None, None, None) == -2
+    p = lpdense.Problem(0, 2, d, d, d)
+    assert lib.lp_solve_dense_noalloc(ctypes.byref(p), None, ctypes.byref(o), None) == -1
 
 
 def test_batch_host_validation_without_device():
