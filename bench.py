@@ -10,8 +10,13 @@ solution read-out.  Inputs are resident in HBM before the timed region.
 Prints one JSON line (rank 0).  `value` is pivots per second over the K timed
 steps; `roofline` relates the persistent kernel's algorithmic bytes
 (16 (m+1)(n+m+1) per pivot) to its average duration measured with HIP events
-on the stream the kernel runs on; `cpu_baseline` times the CPU oracle on a
-bounded sample of the same LP (its first pivots) on this host.
+on the stream the kernel runs on, and gives the measured HBM traffic rate
+from the committed rocprofv3 counters; `cpu_baseline` times the CPU oracle
+on a bounded sample of the same LP (its first pivots) on this host, with all
+the cores the process may use and with one thread.  The same line carries
+the rest of the metric: the same LP on the other schedules, the 64 x 64 LP
+(`small_lp`), the shape sweep (`shapes`), the batched workload (`batch`) and
+the served workload at three arrival rates (`serve`).
 """
 from __future__ import annotations
 
@@ -33,42 +38,94 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, b, c, target_s: float):
-    """Oracle pivots/s on this host: time the first pivots of the same LP.
+def host_cpu():
+    """CPU model, sockets and physical cores of this host (from
+    /proc/cpuinfo), and the logical CPUs this process may run on."""
+    model, phys, cores_per = "unknown", set(), {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            cur = {}
+            for line in f.read().splitlines() + [""]:
+                if not line.strip():
+                    if cur:
+                        model = cur.get("model name", model)
+                        pid = cur.get("physical id", "0")
+                        phys.add(pid)
+                        cores_per[pid] = int(cur.get("cpu cores", "1"))
+                    cur = {}
+                    continue
+                k, _, v = line.partition(":")
+                cur[k.strip()] = v.strip()
+    except OSError:
+        pass
+    sockets = max(len(phys), 1)
+    physical = sum(cores_per.values()) if cores_per else (os.cpu_count() or 1)
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"model": model, "sockets": sockets, "physical_cores": physical, "logical_cpus_allowed": allowed}
 
-    Runs the oracle with max_iter = 0 (Table 1 build only) and with max_iter
-    = K; the difference over K is the per-pivot time.  K grows until the
-    pivot part takes about `target_s` seconds (bounded sample)."""
+
+def _oracle_rate(A, b, c, target_s: float, samples: int, lib_path=None):
+    """Oracle pivots/s on the first pivots of (A, b, c): each sample runs the
+    oracle with max_iter = 0 (Table 1 build only) and with max_iter = K; the
+    difference over K is the time per pivot.  K is sized so that the pivot
+    part of a sample takes about target_s / samples.  Returns the median rate
+    and the samples."""
+    import numpy as np
+
     import oracle
-    t0 = time.perf_counter()
-    r0 = oracle.solve(A, b, c, max_iter=0)
-    t_build = time.perf_counter() - t0
-    K = 2
-    t0 = time.perf_counter()
-    r = oracle.solve(A, b, c, max_iter=K)
-    t_k = time.perf_counter() - t0
-    per = max((t_k - t_build) / max(r.iterations, 1), 1e-9)
-    K2 = int(max(1, min(10_000, target_s / per)))
-    if K2 > K:
+
+    def timed(k):
         t0 = time.perf_counter()
-        r = oracle.solve(A, b, c, max_iter=K2)
-        t_k = time.perf_counter() - t0
-        K = K2
-    piv = max(r.iterations, 1)
-    rate = piv / max(t_k - t_build, 1e-9)
-    assert r0.iterations == 0
-    return {"value": rate, "unit": "pivots/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {piv} pivots of the same {A.shape[0]}x{A.shape[1]} LP "
-                      f"(oracle run with max_iter={K} minus a max_iter=0 build-only run; "
-                      f"{t_k:.1f} s total, single thread, gcc -O3)"}
+        r = oracle.solve(A, b, c, max_iter=k, lib_path=lib_path)
+        return time.perf_counter() - t0, r.iterations
+
+    t_build, _ = timed(0)
+    t2, it2 = timed(2)
+    per = max((t2 - t_build) / max(it2, 1), 1e-9)
+    K = int(max(2, min(10_000, target_s / samples / per)))
+    rates, Ks = [], []
+    for _ in range(samples):
+        tb, _ = timed(0)
+        tk, it = timed(K)
+        rates.append(max(it, 1) / max(tk - tb, 1e-9))
+        Ks.append(it)
+    return float(np.median(rates)), rates, Ks[0]
 
 
-def counter_traffic(pivots_per_launch: int):
-    """HBM bytes per launch from the committed PMC summary of the solve kernel,
-    or None when the kernel sources changed since the counters were taken or
-    the launch is not the one they were taken on."""
+def cpu_baseline(A, b, c, target_s: float, samples: int = 3):
+    """The CPU oracle on this host (a reported baseline, never the target):
+    with every physical core this process may use (the OpenMP build of the
+    same source: Step 5's rows in threads, every value unchanged) and with one
+    thread; median of `samples` samples each."""
+    import oracle
+    host = host_cpu()
+    omp_env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(host["physical_cores"], host["logical_cpus_allowed"])
+    if omp_env > 0:
+        threads = min(threads, omp_env)
+    lib = oracle.load_omp()
+    used = lib.oracle_threads(threads)
+    multi, multi_s, k_multi = _oracle_rate(A, b, c, target_s * 0.5, samples, lib_path=oracle._LIB_OMP)
+    single, single_s, k_single = _oracle_rate(A, b, c, target_s * 0.5, samples)
+    m, n = A.shape
+    return {"value": multi, "unit": "pivots/s", "cores": used, "kind": "oracle",
+            "sample": f"first {k_multi} pivots of the same {m}x{n} LP per sample, median of {samples} samples "
+                      f"(each: oracle run with max_iter=K minus a max_iter=0 build-only run), gcc -O3 with "
+                      f"OpenMP over Step 5's rows, {used} threads",
+            "samples": [round(v, 2) for v in multi_s],
+            "single_thread": {"value": single, "unit": "pivots/s", "cores": 1,
+                              "sample": f"first {k_single} pivots per sample, median of {samples}",
+                              "samples": [round(v, 2) for v in single_s]},
+            "host": host}
+
+
+def counter_traffic(name: str, pivots_per_launch: int):
+    """HBM bytes per launch from the committed PMC summary
+    profiles/<name>_counters.json (FETCH_SIZE and WRITE_SIZE scaled by a
+    plain copy of known size), or None when the kernel sources changed since
+    the counters were taken or the launch is not the one they were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "grid_solve_kernel_dense8192_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -82,6 +139,16 @@ def counter_traffic(pivots_per_launch: int):
     return (d["fetch_size_kib"] * d["fetch_scale"] + d["write_size_kib"] * d["write_scale"]) * 1024.0
 
 
+def traffic_fields(traffic_bytes, avg_ms, algorithmic_bytes):
+    """roofline traffic as a rate (GB/s, the unit of `achieved`), per launch,
+    and as a ratio to the algorithmic bytes; None fields when unmeasured."""
+    if traffic_bytes is None:
+        return {"traffic": None, "traffic_GB_per_launch": None, "traffic_over_algorithmic": None}
+    return {"traffic": round(traffic_bytes / (avg_ms / 1e3) / 1e9, 1),
+            "traffic_GB_per_launch": round(traffic_bytes / 1e9, 1),
+            "traffic_over_algorithmic": round(traffic_bytes / algorithmic_bytes, 4)}
+
+
 def single_schedule(m, n, full_tableau):
     """Best one-LP schedule for a comparison against batching: the LDS
     workgroup when the tableau fits in LDS, else the grid on the tableau form
@@ -92,7 +159,7 @@ def single_schedule(m, n, full_tableau):
     return lpdense.SCHED_GRID_CONDENSED
 
 
-def batch_bench(args):
+def batch_summary(args, steps: int, warmup: int):
     """Batched workload: one lp_solve_batch call on 1024 LPs with m, n
     log-uniform in [32, 1024] (seed 0) per step, against solving the same
     resident LPs one lp_solve_dense_ex call at a time on the same stream."""
@@ -107,11 +174,11 @@ def batch_bench(args):
     stream = torch.cuda.current_stream()
     kw = dict(team_size=args.team_size, team_min_bytes=args.team_min_bytes, wave_slots=args.wave_slots,
               full_tableau=args.full_tableau, stream=stream)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         lpdense.solve_batch(pb, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         lpdense.solve_batch(pb, **kw)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -120,8 +187,8 @@ def batch_bench(args):
     R = pb.m + 1
     W = pb.n + pb.m + 1 if args.full_tableau else pb.n + 1  # stored columns + RHS
     bytes_step = float(np.sum(piv * 16.0 * R * W))
-    lps_s = args.batch_count * args.steps / el
-    log(f"batched: {el * 1e3 / args.steps:.2f} ms/step, {lps_s:.1f} LPs/s, statuses {np.bincount(st)}")
+    lps_s = args.batch_count * steps / el
+    log(f"batched: {el * 1e3 / steps:.2f} ms/step, {lps_s:.1f} LPs/s, statuses {np.bincount(st)}")
     # One LP per call, same resident inputs, same stream.
     views = []
     for i in range(pb.count):
@@ -141,25 +208,31 @@ def batch_bench(args):
     el1 = time.perf_counter() - t0
     single_lps_s = pb.count / el1
     log(f"one at a time: {el1 * 1e3:.1f} ms for {pb.count} LPs, {single_lps_s:.1f} LPs/s")
+    return {"workload": f"batched: {args.batch_count} dense LPs, m and n log-uniform in "
+                        f"[{args.batch_lo}, {args.batch_hi}], seed {args.seed}, one lp_solve_batch call per step",
+            "LPs_per_s": round(lps_s, 2), "ms_per_step": round(el * 1e3 / steps, 3), "steps": steps,
+            "statuses_optimal": int(np.sum(st == lpdense.OPTIMAL)),
+            "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / steps), 1),
+            "effective_GBps": round(bytes_step / (el / steps) / 1e9, 1),
+            "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
+            "one_at_a_time_effective_GBps": round(bytes_step / el1 / 1e9, 1),
+            "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
+            "team_size": args.team_size, "team_min_bytes": args.team_min_bytes,
+            "wave_slots": args.wave_slots, "tableau": "full" if args.full_tableau else "condensed"}
+
+
+def batch_bench(args):
+    b = batch_summary(args, args.steps, args.warmup)
     out = {
-        "metric": METRIC, "value": round(lps_s, 2), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 3), "higher_is_better": True,
+        "metric": METRIC, "value": b["LPs_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batched: {args.batch_count} dense LPs, m and n log-uniform in "
-                               f"[{args.batch_lo}, {args.batch_hi}], "
-                               f"seed {args.seed}, one lp_solve_batch call per step",
-                   "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / args.steps), 1),
-                   "effective_GBps": round(bytes_step / (el / args.steps) / 1e9, 1),
-                   "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
-                   "one_at_a_time_effective_GBps": round(bytes_step / el1 / 1e9, 1),
-                   "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
-                   "team_size": args.team_size, "team_min_bytes": args.team_min_bytes,
-                   "wave_slots": args.wave_slots, "tableau": "full" if args.full_tableau else "condensed"},
+        "config": b,
     }
     print(json.dumps(out), flush=True)
 
 
-def serve_bench(args):
+def serve_summary(args, rates, n_requests: int, n_warmup: int):
     """Served workload: Poisson arrivals of dense LPs (m, n log-uniform in
     [64, 4096], seed-fixed pool) submitted from the host to one lpd_server
     with a footprint budget; per arrival rate, p50/p99 latency (submit to
@@ -171,7 +244,6 @@ def serve_bench(args):
 
     from paper_1804_04737_amd import lpdense, lpgen
     lpdense.load()
-    rates = [float(r) for r in args.serve_rates.split(",")]
     # Requests live in pinned host memory, as a serving front end would keep them.
     keep = []
     def pinned(a):
@@ -181,7 +253,7 @@ def serve_bench(args):
     pool = [tuple(pinned(v) for v in lp) for lp in lpgen.batch_lps(args.serve_pool, 64, 4096, args.seed)]
     log(f"pool of {len(pool)} LPs generated (pinned host memory)")
     rng = np.random.default_rng(args.seed + 1)
-    picks = [int(v) for v in rng.integers(0, len(pool), size=args.serve_requests)]
+    picks = [int(v) for v in rng.integers(0, len(pool), size=n_requests)]
     dev = torch.device("cuda")
 
     # One at a time: host inputs copied in, solved, x copied back, per request.
@@ -210,8 +282,8 @@ def serve_bench(args):
     sweep = []
     n_req = len(picks)
     for rate in rates:
-        arr = lpgen.poisson_arrivals(rate, n_req + args.serve_warmup, args.seed + int(rate))
-        reqs = [pool[p] for p in rng.integers(0, len(pool), size=args.serve_warmup)] + [pool[p] for p in picks]
+        arr = lpgen.poisson_arrivals(rate, n_req + n_warmup, args.seed + int(rate))
+        reqs = [pool[p] for p in rng.integers(0, len(pool), size=n_warmup)] + [pool[p] for p in picks]
         with lpdense.Server(int(args.budget_gb * 1e9), pivots_per_epoch=args.pivots_per_epoch,
                             epoch_bytes_per_wg=int(args.epoch_mb * (1 << 20)),
                             team_bytes_per_wg=int(args.share_kb * 1024),
@@ -230,7 +302,7 @@ def serve_bench(args):
                 time.sleep(min(max(wait, 0.0), 0.0005))
             st = srv.stats()
         # The first requests warm the server up; statistics cover the rest.
-        measured = set(ids[args.serve_warmup:])
+        measured = set(ids[n_warmup:])
         bad = [d for d in done if d.status != lpdense.OPTIMAL]
         done = [d for d in done if d.id in measured]
         lat = np.array([d.latency for d in done]) * 1e3
@@ -244,21 +316,28 @@ def serve_bench(args):
         log(f"rate {rate:g}/s: {row}")
         sweep.append(row)
     top = sweep[-1]
+    return {"workload": f"served: Poisson arrivals of {n_warmup} warm-up + {len(picks)} timed dense "
+                        f"LPs per rate drawn from a pool of "
+                        f"{len(pool)} (m, n log-uniform in [64, 4096], seed {args.seed}), footprint budget "
+                        f"{args.budget_gb:g} GB, {args.max_resident or 'default'} resident slots, "
+                        + (f"{args.pivots_per_epoch} pivots per LP per epoch" if args.pivots_per_epoch > 0
+                           else f"pivot budgets sized for {args.epoch_mb:g} MiB per workgroup per epoch"),
+            "tableau": "full" if args.full_tableau else "condensed",
+            "LPs_per_s_at_top_rate": top["LPs_per_s"],
+            "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
+            "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
+            "one_at_a_time_effective_GBps": round(b1 / el1 / 1e9, 1),
+            "speedup_vs_one_at_a_time": round(top["LPs_per_s"] / single_lps_s, 2) if n1 else None,
+            "sweep": sweep}
+
+
+def serve_bench(args):
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    sv = serve_summary(args, rates, args.serve_requests, args.serve_warmup)
     out = {
-        "metric": METRIC, "value": top["LPs_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": len(rates),
+        "metric": METRIC, "value": sv["LPs_per_s_at_top_rate"], "unit": "LPs/s", "n_gpus": 1, "steps": len(rates),
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"served: Poisson arrivals of {args.serve_warmup} warm-up + {len(picks)} timed dense "
-                               f"LPs per rate drawn from a pool of "
-                               f"{len(pool)} (m, n log-uniform in [64, 4096], seed {args.seed}), footprint budget "
-                               f"{args.budget_gb:g} GB, {args.max_resident or 'default'} resident slots, " + (f"{args.pivots_per_epoch} pivots per LP per epoch" if args.pivots_per_epoch > 0
-                                 else f"pivot budgets sized for {args.epoch_mb:g} MiB per workgroup per epoch"),
-                   "tableau": "full" if args.full_tableau else "condensed",
-                   "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
-                   "one_at_a_time_LPs_per_s": round(single_lps_s, 2),
-                   "one_at_a_time_effective_GBps": round(b1 / el1 / 1e9, 1),
-                   "speedup_vs_one_at_a_time": round(top["LPs_per_s"] / single_lps_s, 2) if n1 else None,
-                   "sweep": sweep},
+        "dtype": "f64", "data": "synthetic", "config": sv,
     }
     print(json.dumps(out), flush=True)
 
@@ -319,6 +398,91 @@ def shapes_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def small_lp_summary(args, calls: int = 400):
+    """The 64 x 64 LP (seed 0, 13 pivots): back-to-back lp_solve_dense calls
+    on one stream with resident inputs and outputs (the LDS-resident
+    workgroup schedule the library picks for it), timed with HIP events."""
+    import torch
+
+    from paper_1804_04737_amd import lpdense, lpgen
+    A, b, c = lpgen.dense_lp(64, 64, 0)
+    dev = torch.device("cuda:0")
+    tA, tb, tc = (torch.from_numpy(v).to(dev) for v in (A, b, c))
+    stream = torch.cuda.current_stream()
+    out = {"workload": "dense LP m = n = 64, seed 0, full solve, lp_solve_dense (auto schedule)"}
+    x = torch.empty(64, dtype=torch.float64, device=dev)
+    obj = torch.empty(1, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    r = lpdense.solve_dense_ex(tA, tb, tc, stream=stream)
+    torch.cuda.synchronize()
+    piv = int(r.iterations.item())
+    for _ in range(20):
+        lpdense.solve_dense(tA, tb, tc, x, obj, st, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(calls):
+        lpdense.solve_dense(tA, tb, tc, x, obj, st, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    us = e0.elapsed_time(e1) * 1e3 / calls
+    out.update({"pivots": piv, "status": lpdense.STATUS_NAMES[int(st.item())], "calls": calls,
+                "us_per_solve": round(us, 2), "pivots_per_s": round(piv / (us * 1e-6), 1),
+                "solves_per_s": round(1e6 / us, 1), "host_us_per_call": round(wall * 1e6 / calls, 2)})
+    log(f"64x64: {out}")
+    return out
+
+
+CONFIG_SHAPES = [(4096, 4096), (8192, 1024), (1024, 8192), (2048, 8192)]
+
+
+def shapes_summary(args, reps: int = 2):
+    """4096 x 4096 and the primal-like / dual-like shapes 8192 x 1024,
+    1024 x 8192 and 2048 x 8192 (seed 0, full solves) on the four grid
+    schedules: pivots, ms per solve, pivots/s, GB/s of each schedule's own
+    bytes per sweep and its fraction of 8 TB/s (HIP events, mean of `reps`
+    solves after one warm-up solve)."""
+    import torch
+
+    from paper_1804_04737_amd import lpdense, lpgen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for m, n in CONFIG_SHAPES:
+        A, b, c = lpgen.dense_lp(m, n, args.seed)
+        tA, tb, tc = (torch.from_numpy(v).to(dev) for v in (A, b, c))
+        row = {"m": m, "n": n}
+        for name, sched, cols, paired in (("full", lpdense.SCHED_AUTO, n + m + 1, False),
+                                          ("condensed", lpdense.SCHED_GRID_CONDENSED, n + 1, False),
+                                          ("paired", lpdense.SCHED_GRID_PAIRED, n + m + 1, True),
+                                          ("condensed_paired", lpdense.SCHED_GRID_CONDENSED_PAIRED, n + 1, True)):
+            lpdense.solve_dense_ex(tA, tb, tc, want_y=False, schedule=sched, stream=stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            rs = []
+            for e0, e1 in ev:
+                e0.record(stream)
+                rs.append(lpdense.solve_dense_ex(tA, tb, tc, want_y=False, schedule=sched, stream=stream))
+                e1.record(stream)
+            torch.cuda.synchronize()
+            ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
+            piv = int(rs[0].iterations.item())
+            sweeps = (piv + 1) // 2 if paired else piv
+            gbs = 16.0 * (m + 1) * cols * sweeps / (ms / 1e3) / 1e9
+            row["pivots"] = piv
+            row["status"] = lpdense.STATUS_NAMES[int(rs[0].status.item())]
+            row[name] = {"ms_per_solve": round(ms, 3), "pivots_per_s": round(piv / (ms / 1e3), 1),
+                         "GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"shape {m}x{n}: {row}")
+        rows.append(row)
+        del tA, tb, tc
+    return {"workload": "dense LPs (generator of the 64x64 and 8192x8192 LPs), seed 0, full solves; "
+                        "GBps counts each schedule's own bytes per sweep: 16 (m+1) W with W = n+m+1 (full) "
+                        "or n+1 (condensed), one sweep per pivot or per two (paired)",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,10 +493,18 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-iter", type=int, default=-1, help="pivot cap per solve (-1: solve to the end)")
     ap.add_argument("--grid-blocks", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="CPU work of the oracle baseline (half multi-threaded, half single-threaded)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-condensed", action="store_true",
                     help="dense: skip the extra timing of the same LP on the condensed tableau")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="dense: skip the 64x64 LP, the shape sweep, the batched and the served workloads")
+    ap.add_argument("--extra-serve-rates", default="100,400,1000",
+                    help="dense run's served workload: arrival rates (LPs/s), the last past saturation")
+    ap.add_argument("--extra-serve-requests", type=int, default=500, help="dense run: timed requests per rate")
+    ap.add_argument("--extra-serve-warmup", type=int, default=50, help="dense run: untimed requests per rate")
+    ap.add_argument("--extra-batch-steps", type=int, default=5, help="dense run: timed lp_solve_batch calls")
     ap.add_argument("--phases", action="store_true",
                     help="after the timed steps, run one more solve with per-phase device timestamps")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -447,11 +619,14 @@ def main():
     bytes_per_pivot = bytes_per_sweep * sweeps[0] / max(pivots[0], 1)
     avg_ms = sum(ev_ms) / len(ev_ms)
     achieved = bytes_per_sweep * (sum(sweeps) / args.steps) / (avg_ms / 1e3) / 1e9
-    traffic = (counter_traffic(pivots[0]) if (m, n, args.seed) == (8192, 8192, 0) and args.schedule == "auto"
-               and args.generator == "dense" else None)
+    headline_lp = (m, n, args.seed) == (8192, 8192, 0) and args.generator == "dense" and args.max_iter < 0
+    counters = {"auto": "grid_solve_kernel_dense8192", "condensed": "grid_solve_kernel_condensed_dense8192",
+                "paired": "grid_solve_kernel_paired_dense8192",
+                "condensed_paired": "grid_solve_kernel_condensed_paired_dense8192"}
+    traffic = counter_traffic(counters[args.schedule], pivots[0]) if headline_lp else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic / 1e9, 1)}
+                **traffic_fields(traffic, avg_ms, bytes_per_sweep * sweeps[0])}
 
     phases = None
     if args.phases:
@@ -477,7 +652,7 @@ def main():
     # Same LP on the condensed tableau and with two pivots per sweep
     # (bitwise-identical results, fewer bytes per pivot): reported beside the
     # full-tableau figures.
-    def other_schedule(sc, bytes_per_sweep_sc, sweeps_of):
+    def other_schedule(sc, bytes_per_sweep_sc, sweeps_of, counter_name):
         lpdense.solve_dense_ex(tA, tb, tc, max_iter=args.max_iter, schedule=sc, want_y=False, stream=stream)
         cs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         ce = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -491,21 +666,38 @@ def main():
         cms = sum(x.elapsed_time(y) for x, y in zip(cs, ce)) / args.steps
         cpiv = int(rs[0].iterations.item())
         same = all(bool(torch.equal(r.x.view(torch.int64), results[0].x.view(torch.int64))) for r in rs)
+        alg = bytes_per_sweep_sc * sweeps_of(cpiv)
+        tr = counter_traffic(counter_name, cpiv) if headline_lp else None
         return {"pivots_per_s": round(cpiv / (cms / 1e3), 2), "ms_per_solve": round(cms, 3),
                 "pivots_per_step": cpiv, "sweeps_per_step": sweeps_of(cpiv),
                 "bytes_per_sweep": int(bytes_per_sweep_sc),
-                "stored_bytes_GBps": round(bytes_per_sweep_sc * sweeps_of(cpiv) / (cms / 1e3) / 1e9, 1),
+                "stored_bytes_GBps": round(alg / (cms / 1e3) / 1e9, 1),
+                "frac_of_hbm_peak": round(alg / (cms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                **traffic_fields(tr, cms, alg),
                 "x_bitwise_equal_to_full_tableau": same}
 
     condensed = paired = condensed_paired = None
     if args.schedule == "auto" and not args.no_condensed:
-        condensed = other_schedule(lpdense.SCHED_GRID_CONDENSED, 16.0 * (m + 1) * (n + 1), lambda p: p)
+        condensed = other_schedule(lpdense.SCHED_GRID_CONDENSED, 16.0 * (m + 1) * (n + 1), lambda p: p,
+                                   counters["condensed"])
         log(f"condensed tableau: {condensed}")
-        paired = other_schedule(lpdense.SCHED_GRID_PAIRED, 16.0 * (m + 1) * (n + m + 1), lambda p: (p + 1) // 2)
+        paired = other_schedule(lpdense.SCHED_GRID_PAIRED, 16.0 * (m + 1) * (n + m + 1), lambda p: (p + 1) // 2,
+                                counters["paired"])
         log(f"two pivots per sweep: {paired}")
         condensed_paired = other_schedule(lpdense.SCHED_GRID_CONDENSED_PAIRED, 16.0 * (m + 1) * (n + 1),
-                                          lambda p: (p + 1) // 2)
+                                          lambda p: (p + 1) // 2, counters["condensed_paired"])
         log(f"two pivots per sweep of the condensed tableau: {condensed_paired}")
+
+    extras = {}
+    if not args.no_extras:
+        # The rest of the metric on the same GPU: the 64 x 64 LP, the shape
+        # sweep, the batched workload and the served one.
+        del results
+        extras["small_lp"] = small_lp_summary(args)
+        extras["shapes"] = shapes_summary(args)
+        extras["batch"] = batch_summary(args, args.extra_batch_steps, 1)
+        extras["serve"] = serve_summary(args, [float(r) for r in args.extra_serve_rates.split(",")],
+                                        args.extra_serve_requests, args.extra_serve_warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -539,8 +731,14 @@ def main():
                    "two_pivots_per_sweep": paired, "condensed_two_pivots_per_sweep": condensed_paired},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
+    # Orderly teardown before the interpreter exits: no kernel in flight and
+    # no cached device memory left to torch's exit path.
+    del tA, tb, tc
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

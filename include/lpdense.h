@@ -61,9 +61,12 @@ typedef enum lpd_status {
     LPD_ITERATION_LIMIT = 2,  /* max_iter pivots done, not yet optimal */
     LPD_INFEASIBLE_START = 3, /* some b_i < 0: slack basis infeasible */
     LPD_NUMERICAL = 4,        /* NaN/Inf in the input or met while pivoting */
-    LPD_DEVICE_TIMEOUT = 5,   /* a grid-wide barrier of the persistent kernel did not
-                                 complete within its watchdog time (about 10 s); the
-                                 outputs are undefined.  Not expected in normal use. */
+    LPD_DEVICE_TIMEOUT = 5,   /* a barrier wait of the persistent grid kernel did not
+                                 complete within its watchdog time (lpd_options.watchdog_us,
+                                 default 10 s): every workgroup gave up and the kernel
+                                 returned.  Only `status` is valid then; x, obj, y,
+                                 iterations, trace, basis and tableau are undefined.  Not
+                                 expected in normal use. */
     LPD_INFEASIBLE = 6        /* lp_solve_general only: phase I ends with artificial
                                  variables left positive, no feasible point */
 } lpd_status;
@@ -133,6 +136,9 @@ typedef struct lpd_options {
     int64_t max_iter;  /* pivot cap (< 0: 50*(m+n); 0 allowed) */
     int32_t schedule;  /* lpd_schedule */
     int32_t grid_blocks; /* grid schedule: workgroups to launch (0: one per CU, capped by co-residency) */
+    int64_t watchdog_us; /* grid schedules: bound of every barrier wait in microseconds, after which
+                            the solve gives up with LPD_DEVICE_TIMEOUT (0: 10 s; < 0: no wait at
+                            all, every barrier gives up at once -- for tests of that path) */
 } lpd_options;
 
 /* Outputs (device pointers; NULL skips an optional output). */

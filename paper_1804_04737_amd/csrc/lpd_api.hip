@@ -40,6 +40,30 @@ struct DeviceInfo {
 std::once_flag g_once[kMaxDevices];
 DeviceInfo g_info[kMaxDevices];
 
+// Devices whose default memory pool the library set to keep freed
+// workspace (bit d: device d), and the teardown that undoes it at process
+// exit: it runs before the HIP runtime's own teardown (registered after the
+// runtime started), synchronises the device, restores the pool's release
+// threshold and returns what the pool still holds.
+std::atomic<uint64_t> g_pool_devices{0};
+std::once_flag g_exit_once;
+
+void release_pools_at_exit() {
+  const uint64_t mask = g_pool_devices.exchange(0);
+  for (int d = 0; d < kMaxDevices; ++d) {
+    if (!((mask >> d) & 1u)) continue;
+    if (hipSetDevice(d) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess) {
+      uint64_t threshold = 0;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+      (void)hipMemPoolTrimTo(pool, 0);
+    }
+  }
+  (void)hipGetLastError();
+}
+
 int device_info(DeviceInfo* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LPD_ERR_DEVICE;
@@ -51,11 +75,7 @@ int device_info(DeviceInfo* out) {
     if (!p.cooperativeLaunch) return;
     // Keep freed workspace in the stream-ordered pool instead of returning it
     // to the device driver after every solve.
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t threshold = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
-    }
+    keep_freed_pool_memory(dev);
     g_info[dev].ncu = p.multiProcessorCount;
     g_info[dev].ok = true;
   });
@@ -95,8 +115,11 @@ int resolve_options(const lpd_problem* prob, const lpd_options* opt, SolveArgs* 
     if (opt->max_iter >= 0) max_iter = opt->max_iter;
     if (opt->schedule < LPD_SCHED_AUTO || opt->schedule > LPD_SCHED_GRID_CONDENSED_PAIRED) return LPD_ERR_INVALID_ARG;
     if (opt->grid_blocks < 0) return LPD_ERR_INVALID_ARG;
+    if (opt->watchdog_us > (INT64_MAX / 100)) return LPD_ERR_INVALID_ARG;
     *schedule = opt->schedule;
     *grid_blocks = opt->grid_blocks;
+    // 100 ticks of the device's real-time clock per microsecond.
+    a->watchdog = opt->watchdog_us < 0 ? -1 : opt->watchdog_us * 100;
   }
   a->eps_d = eps_d;
   a->eps_p = eps_p;
@@ -377,6 +400,16 @@ int solve_dense(const lpd_problem* prob, const lpd_options* opt, const lpd_outpu
 }
 
 }  // namespace
+
+void keep_freed_pool_memory(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess) return;
+  uint64_t threshold = UINT64_MAX;
+  if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold) != hipSuccess) return;
+  g_pool_devices.fetch_or(uint64_t(1) << device);
+  std::call_once(g_exit_once, [] { std::atexit(release_pools_at_exit); });
+}
 
 BatchKnobs tuned_batch_knobs() {
   BatchKnobs k;

@@ -101,6 +101,10 @@ hipError_t launch_batch(const BatchPlan& P, const std::vector<BatchItem>& items,
 int batch_max_blocks(size_t lds_bytes, bool condensed = false);
 // Knobs from the autotune table (built-in defaults when there is none).
 BatchKnobs tuned_batch_knobs();
+// Keeps freed stream-ordered workspace in `device`'s default memory pool
+// (release threshold raised), and registers once the process-exit teardown
+// that synchronises the device, restores the threshold and trims the pool.
+void keep_freed_pool_memory(int device);
 // LDS per workgroup (bytes) of the current device, as the planner uses it.
 int batch_lds_total();
 // Whether the batch kernel can place an LP (lds_total: the device's LDS per

@@ -55,6 +55,10 @@ struct SolveArgs {
   const int32_t* lab0;
   const int32_t* colof0;
   int64_t x_count;  // entries of x written by the read-out (0: n)
+  // Bound of every barrier wait of a multi-workgroup team, in ticks of the
+  // 100 MHz real-time clock: 0 the default (10 s), < 0 none (each wait
+  // gives up at once, for tests of the timeout path).
+  int64_t watchdog;
 };
 
 // Reduction-barrier slot: one per workgroup and per epoch parity, 128 B apart.

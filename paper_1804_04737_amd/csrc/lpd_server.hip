@@ -392,11 +392,7 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   s->lds_limit = (size_t)lds;
   // Keep freed pool memory reserved: admissions and departures allocate and
   // free stream-ordered all the time.
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-    uint64_t keep = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  }
+  keep_freed_pool_memory(device);
   const size_t ns = (size_t)s->nslots;
   bool ok = hipStreamCreate(&s->stream) == hipSuccess;
   ok = ok && hipStreamCreate(&s->copy_stream) == hipSuccess;

@@ -88,11 +88,20 @@ __device__ __forceinline__ T own_sreg(T v) {
   return v;
 }
 
+// Bound of a barrier wait in ticks of the 100 MHz real-time clock, from a
+// solve's watchdog option: 0 the default, > 0 that many ticks, < 0 none at
+// all (every wait gives up at once: a test of the timeout path).
+__device__ __forceinline__ int64_t wait_budget(int64_t watchdog) {
+  return watchdog == 0 ? (int64_t)kWatchdogTicks : watchdog;
+}
+
 // Grid-wide lexicographic arg-min that doubles as the barrier.
 // `c` is this workgroup's reduced candidate (identical in all its threads).
-// Every workgroup returns the same global result.
+// Every workgroup returns the same global result.  A wait that exceeds
+// `budget` ticks (wait_budget; < 0: every wait) gives up and flags
+// kFlagTimeout instead of hanging.
 __device__ Cand grid_reduce(const Team& tm, Cand c, uint32_t epoch, Cand* scratch,
-                            bool diag = false, uint64_t* tk = nullptr) {
+                            bool diag = false, uint64_t* tk = nullptr, int64_t budget = kWatchdogTicks) {
   const int nb = tm.size;
   if (nb == 1) {
     // A one-workgroup team shares nothing across CUs: a workgroup barrier is
@@ -123,16 +132,18 @@ __device__ Cand grid_reduce(const Team& tm, Cand c, uint32_t epoch, Cand* scratc
     __hip_atomic_store(&s->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   Cand got = cand_none();
+  if (budget < 0) got.flags |= kFlagTimeout;  // no wait at all
   bool polled = false;
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  for (int s = threadIdx.x; s < nb; s += blockDim.x) {
+  for (int s = threadIdx.x; s < nb && budget >= 0; s += blockDim.x) {
     // Epochs only grow; a slot written for a later epoch also counts as arrived
     // (its payload lives in the other parity buffer).
     while ((int32_t)(__hip_atomic_load(&buf[s].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
       __builtin_amdgcn_s_sleep(1);
-      // Watchdog: a barrier that has not completed after kWatchdogTicks of the
-      // 100 MHz real-time counter reports a timeout instead of waiting forever.
-      if (__builtin_amdgcn_s_memrealtime() - t0 > kWatchdogTicks) {
+      // Watchdog: a barrier that has not completed after `budget` ticks of
+      // the 100 MHz real-time counter reports a timeout instead of waiting
+      // forever.
+      if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)budget) {
         got.flags |= kFlagTimeout;
         break;
       }
@@ -402,7 +413,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
       Cand f0 = cand_none();
       f0.flags = flags;
       f0 = block_reduce(f0, scratch);
-      const Cand gf = grid_reduce(tm, f0, ++epoch, scratch);
+      const Cand gf = grid_reduce(tm, f0, ++epoch, scratch, false, nullptr, wait_budget(a.watchdog));
       if (gf.flags & kFlagTimeout) status = kDeviceTimeout;
       else if (gf.flags & kFlagNonFinite) status = kNumerical;
       else if (gf.flags & kFlagNegativeB) status = kInfeasibleStart;
@@ -443,7 +454,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         ratio_offer(rc, aik, r, (int32_t)i, a.eps_p);
       }
       rc = block_reduce(rc, scratch);
-      const Cand gr = grid_reduce(tm, rc, ++epoch, scratch);
+      const Cand gr = grid_reduce(tm, rc, ++epoch, scratch, false, nullptr, wait_budget(a.watchdog));
       if (gr.flags & kFlagTimeout) status = kDeviceTimeout;
       else if (gr.flags & kFlagNonFinite) status = kNumerical;
       else if (gr.i == kNoIndex) status = kUnbounded;
@@ -788,10 +799,13 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
         if (tid == 0) {
           const uint32_t target = (uint32_t)nb * (uint32_t)(rnd + 1);
           const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-          while ((int32_t)(__hip_atomic_load(w.tickets + kPairCountWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+          const int64_t budget = wait_budget(a.watchdog);
+          if (budget < 0) rc.flags |= kFlagTimeout;
+          while (budget >= 0 &&
+                 (int32_t)(__hip_atomic_load(w.tickets + kPairCountWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
                            target) < 0) {
             __builtin_amdgcn_s_sleep(1);
-            if (__builtin_amdgcn_s_memrealtime() - t0 > kWatchdogTicks) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)budget) {
               rc.flags |= kFlagTimeout;
               break;
             }
@@ -1146,7 +1160,7 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     rc = block_reduce(rc, scratch);
     if (tid == 0) *cap_count = 0;
     if (tk && tid == 0) tk[2] = __builtin_amdgcn_s_memrealtime();
-    const Cand gr = grid_reduce(tm, rc, ++epoch, scratch, a.phase_ticks != nullptr, tk);
+    const Cand gr = grid_reduce(tm, rc, ++epoch, scratch, a.phase_ticks != nullptr, tk, wait_budget(a.watchdog));
 
     // ---- loop control (identical decision in every workgroup)
     if constexpr (FU) {
@@ -1194,6 +1208,12 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     return;
   }
   if (a.state && leader && tid == 0) a.state->phase = 2;
+  if (status == kDeviceTimeout) {
+    // Some workgroup gave up waiting: the workspace may be incomplete (even
+    // the index arrays of Step 1), so nothing is read back but the status.
+    if (leader && tid == 0) *a.status = status;
+    return;
+  }
 
   // ---------------- solution read-out ----------------
   const double* rhs_f = w.rhs[fpar];

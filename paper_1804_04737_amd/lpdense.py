@@ -36,7 +36,7 @@ class Problem(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("eps_d", ctypes.c_double), ("eps_p", ctypes.c_double), ("max_iter", _I64),
-                ("schedule", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("watchdog_us", _I64)]
 
 
 class Outputs(ctypes.Structure):
@@ -192,7 +192,8 @@ class DenseResult:
 def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter: int = -1,
                    schedule: int = SCHED_AUTO, grid_blocks: int = 0, want_y: bool = True,
                    trace_cap: int = 0, want_basis: bool = False, want_tableau: bool = False,
-                   phase_cap: int = 0, stream=None, noalloc: bool = False) -> DenseResult:
+                   phase_cap: int = 0, stream=None, noalloc: bool = False,
+                   watchdog_us: int = 0) -> DenseResult:
     """lp_solve_dense_ex on device tensors; outputs are freshly allocated
     device tensors (asynchronous: synchronise the stream before reading).
     noalloc=True calls lp_solve_dense_noalloc instead (the library's fixed
@@ -216,7 +217,7 @@ def solve_dense_ex(A, b, c, *, eps_d: float = 0.0, eps_p: float = 0.0, max_iter:
         phase_ticks=torch.zeros((phase_cap, 8), dtype=i64, device=dev) if phase_cap > 0 else None,
     )
     prob = Problem(m, n, A.data_ptr(), b.data_ptr(), c.data_ptr())
-    opts = Options(float(eps_d), float(eps_p), int(max_iter), int(schedule), int(grid_blocks))
+    opts = Options(float(eps_d), float(eps_p), int(max_iter), int(schedule), int(grid_blocks), int(watchdog_us))
     outs = Outputs(res.x.data_ptr(), res.obj.data_ptr(), res.status.data_ptr(),
                    res.y.data_ptr() if res.y is not None else None,
                    res.iterations.data_ptr(),
