@@ -64,6 +64,7 @@ __device__ __forceinline__ dbl2 ld_stream(const dbl2* p) {
   return __builtin_nontemporal_load((const gdbl2*)p);
 }
 __device__ __forceinline__ void st_stream(dbl2* p, dbl2 v) { __builtin_nontemporal_store(v, (gdbl2*)p); }
+
 // Plain loads and stores of workspace vectors, through global pointers.
 typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ double gld(const double* p) { return *(const gdouble*)p; }
@@ -150,11 +151,14 @@ __device__ Cand grid_reduce(const Team& tm, Cand c, uint32_t epoch, Cand* scratc
     }
     polled = true;
   }
-  if (polled || threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  if (tk) {
-    __syncthreads();
-    if (threadIdx.x == 0) tk[5] = __builtin_amdgcn_s_memrealtime();
-  }
+  (void)polled;
+  // One agent-scope acquire per workgroup (it invalidates this CU's L1 and
+  // the XCD's L2, which every wave of the workgroup shares), after every
+  // slot has been seen and before any wave reads a payload.
+  __syncthreads();
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  if (tk && threadIdx.x == 0) tk[5] = __builtin_amdgcn_s_memrealtime();
   uint64_t ta = 0, tp = 0;
   for (int s = threadIdx.x; s < nb; s += blockDim.x) {
     Cand o;
