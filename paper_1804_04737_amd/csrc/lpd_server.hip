@@ -15,8 +15,9 @@
 //              bytes per epoch: all of them advance together and finish the
 //              epoch at about the same time;
 //   retire     statuses come back; finished LPs copy x to the caller's host
-//              buffer, their memory returns to the budget and a completion
-//              with host timestamps is queued for lpd_server_poll.
+//              buffer on a third stream while the next epoch already runs,
+//              then their memory returns to the budget and a completion with
+//              host timestamps is queued for lpd_server_poll.
 // Requests admitted during epoch E join epoch E+1 (the compute stream waits
 // for their copies), so work from different requests overlaps on the device.
 // Every LP performs exactly the pivots of its own lp_solve_dense call, so its
@@ -82,7 +83,9 @@ struct lpd_server {
   BatchKnobs knobs;
   hipStream_t stream = nullptr;       // compute: epochs, result copies, frees
   hipStream_t copy_stream = nullptr;  // admission: allocations and input copies
+  hipStream_t res_stream = nullptr;   // results: x of finished LPs back to the host
   hipEvent_t ev_staged = nullptr;     // end of the last admission round's copies
+  hipEvent_t ev_xdone = nullptr;      // end of the retiring LPs' x copies
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the epoch launch
   // Slot tables (device): status, objective, pivots and solve state of each
   // resident LP, with pinned host mirrors.  init_status / init_state are
@@ -113,6 +116,10 @@ struct lpd_server {
   lpd_server_stats stats{};   // under mu
   // worker-only state
   std::vector<Request> resident, staged;
+  std::vector<Request> retiring;  // finished in the last epoch, x on its way
+  std::vector<int32_t> retiring_status;
+  std::vector<double> retiring_obj;
+  std::vector<int64_t> retiring_iter;
   std::vector<int32_t> free_slots;
   bool in_flight = false;
   hipError_t epoch_err = hipSuccess;
@@ -124,6 +131,7 @@ struct lpd_server {
   void admit();
   void launch_epoch();
   void retire_epoch();
+  void finish_retiring();
   void release(Request& r);
   void complete(Request& r, int32_t status, double obj, int64_t iters);
 };
@@ -159,9 +167,9 @@ void lpd_server::run() {
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (!in_flight && resident.empty() && staged.empty())
+      if (!in_flight && resident.empty() && staged.empty() && retiring.empty())
         cv.wait(lk, [&] { return stop || !pending.empty(); });
-      if (stop && pending.empty() && !in_flight && resident.empty() && staged.empty()) return;
+      if (stop && pending.empty() && !in_flight && resident.empty() && staged.empty() && retiring.empty()) return;
     }
     admit();  // its copies overlap the epoch in flight
     if (in_flight) retire_epoch();
@@ -171,6 +179,7 @@ void lpd_server::run() {
       staged.clear();
     }
     if (!resident.empty()) launch_epoch();
+    finish_retiring();  // while the new epoch runs
   }
 }
 
@@ -336,25 +345,42 @@ void lpd_server::retire_epoch() {
     stats.epochs += 1;
     if (timed) stats.kernel_seconds += ms * 1e-3;
   }
-  std::vector<Request> still, fin;
+  // Finished LPs: their x goes back on the result stream (the epoch that
+  // wrote it is complete), and they are completed once it has arrived, after
+  // the next epoch has been launched.  Their slot-table entries are read now:
+  // the next epoch's copies overwrite the host mirrors.
+  std::vector<Request> still;
   for (Request& r : resident) {
     const int32_t st = e == hipSuccess ? h_status[r.slot] : (int32_t)LPD_ERR_HIP;
     if (st == -1) {
       still.push_back(r);
     } else {
-      if (st >= 0) (void)hipMemcpyAsync(r.x_out, r.dx, 8 * (size_t)r.n, hipMemcpyDeviceToHost, stream);
-      fin.push_back(r);
+      if (st >= 0) (void)hipMemcpyAsync(r.x_out, r.dx, 8 * (size_t)r.n, hipMemcpyDeviceToHost, res_stream);
+      retiring.push_back(r);
+      retiring_status.push_back(st);
+      retiring_obj.push_back(h_obj[r.slot]);
+      retiring_iter.push_back(h_iter[r.slot]);
     }
   }
-  if (!fin.empty()) (void)hipStreamSynchronize(stream);
-  for (Request& r : fin) {
-    const int32_t st = e == hipSuccess ? h_status[r.slot] : (int32_t)LPD_ERR_HIP;
-    const double obj = h_obj[r.slot];
-    const int64_t iters = h_iter[r.slot];
-    release(r);
-    complete(r, st, obj, iters);
-  }
+  if (!retiring.empty()) (void)hipEventRecord(ev_xdone, res_stream);
   resident.swap(still);
+}
+
+void lpd_server::finish_retiring() {
+  if (retiring.empty()) return;
+  (void)hipEventSynchronize(ev_xdone);
+  // Their memory is freed on the compute stream after the x copies (and
+  // after the epoch just launched, which does not touch it).
+  (void)hipStreamWaitEvent(stream, ev_xdone, 0);
+  for (size_t k = 0; k < retiring.size(); ++k) {
+    Request& r = retiring[k];
+    release(r);
+    complete(r, retiring_status[k], retiring_obj[k], retiring_iter[k]);
+  }
+  retiring.clear();
+  retiring_status.clear();
+  retiring_obj.clear();
+  retiring_iter.clear();
 }
 
 extern "C" {
@@ -396,7 +422,9 @@ lpd_server* lpd_server_create(int device, uint64_t budget_bytes, const lpd_serve
   const size_t ns = (size_t)s->nslots;
   bool ok = hipStreamCreate(&s->stream) == hipSuccess;
   ok = ok && hipStreamCreate(&s->copy_stream) == hipSuccess;
+  ok = ok && hipStreamCreate(&s->res_stream) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&s->ev_staged, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&s->ev_xdone, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreate(&s->ev_k0) == hipSuccess;
   ok = ok && hipEventCreate(&s->ev_k1) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->d_status, 4 * ns) == hipSuccess;
@@ -490,6 +518,7 @@ void lpd_server_destroy(lpd_server* s) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(s->device);
   if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+  if (s->res_stream) (void)hipStreamSynchronize(s->res_stream);
   if (s->stream) {
     if (s->meta) (void)hipFreeAsync(s->meta, s->stream);
     (void)hipStreamSynchronize(s->stream);
@@ -503,9 +532,10 @@ void lpd_server_destroy(lpd_server* s) {
   (void)hipHostFree(s->h_iter);
   (void)hipHostFree(s->init_status);
   (void)hipHostFree(s->init_state);
-  for (hipEvent_t ev : {s->ev_staged, s->ev_k0, s->ev_k1})
+  for (hipEvent_t ev : {s->ev_staged, s->ev_xdone, s->ev_k0, s->ev_k1})
     if (ev) (void)hipEventDestroy(ev);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  if (s->res_stream) (void)hipStreamDestroy(s->res_stream);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   (void)hipSetDevice(prev);
   delete s;
