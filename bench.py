@@ -208,8 +208,14 @@ def batch_summary(args, steps: int, warmup: int):
     el1 = time.perf_counter() - t0
     single_lps_s = pb.count / el1
     log(f"one at a time: {el1 * 1e3:.1f} ms for {pb.count} LPs, {single_lps_s:.1f} LPs/s")
+    tr = None
+    if (args.batch_count, args.batch_lo, args.batch_hi, args.seed) == (1024, 32, 1024, 0) and not args.full_tableau \
+            and (args.team_size, args.team_min_bytes, args.wave_slots) == (0, 0, 0):
+        tr = counter_traffic("batch_kernel_batch1024", int(piv.sum()))
     return {"workload": f"batched: {args.batch_count} dense LPs, m and n log-uniform in "
                         f"[{args.batch_lo}, {args.batch_hi}], seed {args.seed}, one lp_solve_batch call per step",
+            "hbm_traffic_GBps": None if tr is None else round(tr / (el / steps) / 1e9, 1),
+            "hbm_traffic_frac_of_peak": None if tr is None else round(tr / (el / steps) / 1e9 / HBM_PEAK_GBS, 4),
             "LPs_per_s": round(lps_s, 2), "ms_per_step": round(el * 1e3 / steps, 3), "steps": steps,
             "statuses_optimal": int(np.sum(st == lpdense.OPTIMAL)),
             "pivots_per_step": int(piv.sum()), "aggregate_pivots_per_s": round(piv.sum() / (el / steps), 1),
@@ -403,6 +409,19 @@ def shapes_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy: its FETCH_SIZE / WRITE_SIZE
+    readings calibrate the HBM byte counters of the solve kernels."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("copied 1 GiB for counter calibration")
+
+
 def small_lp_summary(args, calls: int = 400):
     """The 64 x 64 LP (seed 0, 13 pivots): back-to-back lp_solve_dense calls
     on one stream with resident inputs and outputs (the LDS-resident
@@ -549,6 +568,8 @@ def main():
               f"(one LP per GPU; sharding over several GPUs is not built).", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration()
     if args.workload == "batch":
         return batch_bench(args)
     if args.workload == "serve":
@@ -571,16 +592,6 @@ def main():
     tc = torch.from_numpy(c).to(dev)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    if args.copy_calibration:
-        # Plain 1 GiB copy: its FETCH_SIZE / WRITE_SIZE readings calibrate the
-        # HBM byte counters of the solve kernel.
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copied 1 GiB for counter calibration")
 
     sched = {"auto": lpdense.SCHED_AUTO, "condensed": lpdense.SCHED_GRID_CONDENSED,
              "paired": lpdense.SCHED_GRID_PAIRED,

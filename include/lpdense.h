@@ -152,15 +152,21 @@ typedef struct lpd_outputs {
     int64_t trace_cap;   /* capacity of trace in pivots */
     int64_t *basis;      /* m, optional: basic variable of each row (0..n+m-1) */
     double *tableau;     /* (m+1)*(n+m+1), optional: final tableau, Table 1 layout */
-    uint64_t *phase_ticks; /* 8*phase_cap, optional (grid schedule only, diagnostics):
-                              per pivot, readings of the device's 100 MHz real-time
-                              clock: [0] pivot start, [1] pricing done, [2] this
-                              workgroup's update share done (all taken by workgroup
-                              0), [3] latest arrival of any workgroup at the pivot's
-                              barrier, [4] latest publication after its release
-                              fence, [5] workgroup 0 saw every arrival, [6] barrier
-                              reduction done, [7] unused.  Untouched on the
-                              workgroup schedule. */
+    uint64_t *phase_ticks; /* 8*phase_cap, optional (grid schedules only, diagnostics):
+                              readings of the device's 100 MHz real-time clock, one
+                              entry of 8 per sweep, at the index of the sweep's first
+                              pivot: [0] sweep start, [1] pricing done, [2] workgroup
+                              0's update share done, [3] latest arrival of any
+                              workgroup at the sweep's barrier, [4] latest publication
+                              after its release fence, [5] workgroup 0 saw every
+                              arrival, [6] barrier reduction done, [7] (two pivots per
+                              sweep only) end of the wait at the pair's publication
+                              barrier.  Entries [0]-[6] of every sweep are written
+                              ([3] and [4] zeroed by workgroup 0, then raised to the
+                              maximum), so they need no initialisation; [7] on the
+                              one-pivot schedules, and the whole entry of a sweep's
+                              second pivot on the paired ones, are left untouched.
+                              Untouched on the workgroup schedule. */
     int64_t phase_cap;     /* capacity of phase_ticks in pivots */
 } lpd_outputs;
 

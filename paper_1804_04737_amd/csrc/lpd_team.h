@@ -476,7 +476,13 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
     if (a.state && a.pivot_budget >= 0 && done_here == a.pivot_budget) break;  // suspend
     ++done_here;
     uint64_t* tk = (ticks && iter < a.phase_cap) ? a.phase_ticks + kTicks * iter : nullptr;
-    if (tk && tid == 0) tk[0] = __builtin_amdgcn_s_memrealtime();
+    if (tk && tid == 0) {
+      tk[0] = __builtin_amdgcn_s_memrealtime();
+      // Entries 3 and 4 are maxima over every workgroup (atomic max after
+      // the barrier has seen this workgroup's arrival): start them at zero.
+      tk[3] = 0;
+      tk[4] = 0;
+    }
     // The previous pivot's ticket counters are idle until the next pivot
     // (every workgroup passed the last barrier after its final ticket): reset
     // them.
