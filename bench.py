@@ -92,6 +92,28 @@ def _oracle_rate(A, b, c, target_s: float, samples: int, lib_path=None):
     return float(np.median(rates)), rates, Ks[0]
 
 
+def host_triad_gbps(threads: int, mib: int = 1024, reps: int = 5):
+    """STREAM-triad bandwidth of this host, a = b + s c on three float64
+    arrays of `mib` MiB each with `threads` CPU threads (torch's CPU kernels),
+    counted as 3 x the array bytes per pass; best of `reps`."""
+    import torch
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        n = mib * (1 << 20) // 8
+        b = torch.ones(n, dtype=torch.float64)
+        c = torch.full((n,), 2.0, dtype=torch.float64)
+        a = torch.empty(n, dtype=torch.float64)
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            torch.add(b, c, alpha=3.0, out=a)
+            best = min(best, time.perf_counter() - t0)
+        return 3 * n * 8 / best / 1e9
+    finally:
+        torch.set_num_threads(prev)
+
+
 def cpu_baseline(A, b, c, target_s: float, samples: int = 3):
     """The CPU oracle on this host (a reported baseline, never the target):
     with every physical core this process may use (the OpenMP build of the
@@ -108,14 +130,23 @@ def cpu_baseline(A, b, c, target_s: float, samples: int = 3):
     multi, multi_s, k_multi = _oracle_rate(A, b, c, target_s * 0.5, samples, lib_path=oracle._LIB_OMP)
     single, single_s, k_single = _oracle_rate(A, b, c, target_s * 0.5, samples)
     m, n = A.shape
+    # The oracle on its own roofline: its Step 5 streams the tableau like the
+    # GPU's sweep, 16 (m+1)(n+m+1) bytes per pivot.
+    bpp = 16.0 * (m + 1) * (n + m + 1)
+    triad_multi, triad_single = host_triad_gbps(used), host_triad_gbps(1)
+    host.update({"stream_triad_GBps": round(triad_multi, 1), "stream_triad_GBps_one_thread": round(triad_single, 1)})
     return {"value": multi, "unit": "pivots/s", "cores": used, "kind": "oracle",
+            "effective_GBps": round(multi * bpp / 1e9, 1),
+            "frac_of_host_triad": round(multi * bpp / 1e9 / triad_multi, 3),
             "sample": f"first {k_multi} pivots of the same {m}x{n} LP per sample, median of {samples} samples "
                       f"(each: oracle run with max_iter=K minus a max_iter=0 build-only run), gcc -O3 with "
                       f"OpenMP over Step 5's rows, {used} threads",
             "samples": [round(v, 2) for v in multi_s],
             "single_thread": {"value": single, "unit": "pivots/s", "cores": 1,
                               "sample": f"first {k_single} pivots per sample, median of {samples}",
-                              "samples": [round(v, 2) for v in single_s]},
+                              "samples": [round(v, 2) for v in single_s],
+                              "effective_GBps": round(single * bpp / 1e9, 1),
+                              "frac_of_host_triad": round(single * bpp / 1e9 / triad_single, 3)},
             "host": host}
 
 

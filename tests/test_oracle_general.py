@@ -190,8 +190,14 @@ def test_reduces_to_the_paper_method_without_artificials():
 
 def test_infeasible_unbounded_and_degenerate_cases():
     A = np.array([[1.0, 1.0], [1.0, 0.0]])
-    r = general.solve_general(A, np.array([-1.0, 5.0]), np.array([1.0, 1.0]), np.array([1, 0], np.int8))
-    assert r.status == general.INFEASIBLE
+    c = np.array([1.0, 1.0])
+    r = general.solve_general(A, np.array([-1.0, 5.0]), c, np.array([1, 0], np.int8))
+    assert r.status == general.INFEASIBLE and abs(r.obj - float(c @ r.x)) <= 1e-12 * (1 + abs(r.obj))
+    for seed in range(120):  # z of every infeasible tiny LP is c^T x of the point returned
+        A, b, cc, sense = _tiny(seed)
+        r = general.solve_general(A, b, cc, sense)
+        if r.status == general.INFEASIBLE:
+            assert abs(r.obj - float(cc @ r.x)) <= 1e-12 * (1 + np.abs(cc).sum() * (1 + np.abs(r.x).max()))
     r = general.solve_general(np.eye(2), np.array([1.0, 2.0]), np.array([1.0, 1.0]), np.array([2, 2], np.int8))
     assert r.status == oracle.UNBOUNDED
     # A square nonsingular equality system: every original variable basic.
