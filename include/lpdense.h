@@ -135,7 +135,9 @@ typedef struct lpd_options {
     double eps_p;      /* ratio-test pivot tolerance (<= 0: 1e-9) */
     int64_t max_iter;  /* pivot cap (< 0: 50*(m+n); 0 allowed) */
     int32_t schedule;  /* lpd_schedule */
-    int32_t grid_blocks; /* grid schedule: workgroups to launch (0: one per CU, capped by co-residency) */
+    int32_t grid_blocks; /* grid schedule: workgroups to launch (0: one per 160 KiB of stored tableau,
+                            in multiples of 8, at least 64 and at most one per CU; always capped
+                            by co-residency) */
     int64_t watchdog_us; /* grid schedules: bound of every barrier wait in microseconds, after which
                             the solve gives up with LPD_DEVICE_TIMEOUT (0: 10 s; < 0: no wait at
                             all, every barrier gives up at once -- for tests of that path) */

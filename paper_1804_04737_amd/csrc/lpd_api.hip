@@ -5,6 +5,7 @@
 #include <dlfcn.h>
 
 #include <atomic>
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -294,6 +295,17 @@ hipError_t upload_start_index(StartIndex* si, int32_t* dev, SolveArgs& a, bool c
   return hipSuccess;
 }
 
+// Grid size when the caller names none: one workgroup per 160 KiB of stored
+// tableau, in multiples of 8 (one per XCD each), at least 64 and at most one
+// per compute unit.  Below about 40 MiB a sweep is short, and the per-pivot
+// barrier costs more with each added workgroup than the added bandwidth
+// saves (measured from 4 to 70 MiB; a count off a multiple of 8 was slower).
+int default_grid_blocks(int64_t m, int64_t n, bool condensed, int ncu) {
+  const double bytes = 8.0 * (double)(m + 1) * (double)((condensed ? n : n + m) + 1);
+  const double want = 8.0 * std::floor(bytes / (160.0 * 1024.0) / 8.0);
+  return (int)std::max(std::min(want, (double)ncu), (double)std::min(64, ncu));
+}
+
 // Runs the solve described by `a` (inputs, options and outputs set) on
 // `schedule`.  The workspace is allocated stream-ordered on `stream`, or
 // (noalloc) taken from `scratch` (kScratchMax bytes, no allocation at all:
@@ -330,7 +342,7 @@ int run_solve(SolveArgs& a, int schedule, int grid_blocks, bool noalloc, const i
   if (a.n == 0) condensed = false;
   const int maxb = grid_max_blocks(a.m, a.n, 0, condensed, paired);
   if (maxb <= 0) return LPD_ERR_TOO_LARGE;
-  int nb = grid_blocks > 0 ? grid_blocks : dev.ncu;
+  int nb = grid_blocks > 0 ? grid_blocks : default_grid_blocks(a.m, a.n, condensed, dev.ncu);
   if (nb > maxb) nb = maxb;
   const GridLayout L = grid_layout(a.m, a.n, nb, condensed, paired);
   if (noalloc) {
