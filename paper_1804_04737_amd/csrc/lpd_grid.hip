@@ -8,12 +8,12 @@
 namespace lpd {
 namespace {
 
-template <int NT, int MAP, bool CD = false, bool PN = false, bool FU = false>
+template <int NT, int MAP, bool CD = false, bool PN = false, bool FU = false, bool TL = false>
 __global__ void __launch_bounds__(NT) grid_solve_kernel(SolveArgs a, GridWork w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   uint32_t epoch = 0;
   const Team tm{(int)blockIdx.x, (int)gridDim.x, w.slots, &epoch};
-  team_solve<NT, MAP, CD, true, PN, FU>(a, w, tm, smem);
+  team_solve<NT, MAP, CD, true, PN, FU, TL>(a, w, tm, smem);
 }
 
 // Clears the barrier slots of a fresh workspace (stream-ordered, no memset node).
@@ -36,6 +36,12 @@ constexpr GridKernel kPanelledCondensed = grid_solve_kernel<kNT, 0, true, true>;
 // Two pivots per sweep (two rows per column panel), full and condensed tableau.
 constexpr GridKernel kPaired = grid_solve_kernel<kNT, 0, false, true, true>;
 constexpr GridKernel kPairedCondensed = grid_solve_kernel<kNT, 0, true, true, true>;
+// The same with plain (temporal) tableau loads, for tableaux that stay
+// resident in the memory-side cache between sweeps.
+constexpr GridKernel kTemporal = grid_solve_kernel<kNT, 0, false, false, false, true>;
+constexpr GridKernel kTemporalCondensed = grid_solve_kernel<kNT, 0, true, false, false, true>;
+constexpr GridKernel kTemporalPaired = grid_solve_kernel<kNT, 0, false, true, true, true>;
+constexpr GridKernel kTemporalPairedCondensed = grid_solve_kernel<kNT, 0, true, true, true, true>;
 
 // LPD_GRID_VARIANT (tuning / diagnostics) picks the thread mapping; 0 by default.
 int variant_index(int64_t) {
@@ -44,10 +50,26 @@ int variant_index(int64_t) {
   return (x >= 0 && x < kNumVariants) ? x : 0;
 }
 
-GridKernel pick_kernel(int64_t vw, bool condensed, bool panelled, bool paired = false) {
-  if (paired) return condensed ? kPairedCondensed : kPaired;
+// Largest stored tableau (constraint rows, bytes) swept with temporal loads:
+// 288 MiB, or LPD_TEMPORAL_MAX_MB (tuning; 0 turns them off).  Read once.
+uint64_t temporal_max_bytes() {
+  static const uint64_t v = [] {
+    const char* e = getenv("LPD_TEMPORAL_MAX_MB");
+    const long x = e ? atol(e) : 288;
+    return (uint64_t)(x > 0 ? x : 0) << 20;
+  }();
+  return v;
+}
+
+GridKernel pick_kernel(const GridLayout& L, int64_t m, bool condensed, bool panelled, bool paired = false) {
+  const bool tl = variant_index(L.vw) == 0 && (uint64_t)m * (uint64_t)L.ld * 8 <= temporal_max_bytes();
+  if (paired) {
+    if (tl) return condensed ? kTemporalPairedCondensed : kTemporalPaired;
+    return condensed ? kPairedCondensed : kPaired;
+  }
   if (panelled) return condensed ? kPanelledCondensed : kPanelled;
-  return condensed ? kCondensed : kVariants[variant_index(vw)];
+  if (tl) return condensed ? kTemporalCondensed : kTemporal;
+  return condensed ? kCondensed : kVariants[variant_index(L.vw)];
 }
 
 int lds_limit() {
@@ -110,8 +132,8 @@ int grid_max_blocks(int64_t m, int64_t n, int nthreads, bool condensed, bool pai
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const int64_t vw = grid_layout(m, n, 1, condensed).vw;
-  auto fn = pick_kernel(vw, condensed, vecs < vw, paired);
+  const GridLayout L = grid_layout(m, n, 1, condensed, paired);
+  auto fn = pick_kernel(L, m, condensed, vecs < L.vw, paired);
   if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0;
@@ -134,7 +156,7 @@ hipError_t launch_grid_solve(const SolveArgs& a, void* workspace, int nblocks, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  auto fn = pick_kernel(L.vw, condensed, w.lds_vecs < L.vw, paired);
+  auto fn = pick_kernel(L, a.m, condensed, w.lds_vecs < L.vw, paired);
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   SolveArgs args = a;
