@@ -51,14 +51,12 @@ int variant_index(int64_t) {
 }
 
 // Largest stored tableau (constraint rows, bytes) swept with temporal loads:
-// 288 MiB, or LPD_TEMPORAL_MAX_MB (tuning; 0 turns them off).  Read once.
+// 288 MiB, or LPD_TEMPORAL_MAX_MB (tuning and tests; 0 turns them off), read
+// at every launch.
 uint64_t temporal_max_bytes() {
-  static const uint64_t v = [] {
-    const char* e = getenv("LPD_TEMPORAL_MAX_MB");
-    const long x = e ? atol(e) : 288;
-    return (uint64_t)(x > 0 ? x : 0) << 20;
-  }();
-  return v;
+  const char* e = getenv("LPD_TEMPORAL_MAX_MB");
+  const long x = e ? atol(e) : 288;
+  return (uint64_t)(x > 0 ? x : 0) << 20;
 }
 
 GridKernel pick_kernel(const GridLayout& L, int64_t m, bool condensed, bool panelled, bool paired = false) {

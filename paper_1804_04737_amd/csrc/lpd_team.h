@@ -141,59 +141,70 @@ __device__ Cand grid_reduce(const Team& tm, Cand c, uint32_t epoch, Cand* scratc
     }
     __hip_atomic_store(&s->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  Cand got = cand_none();
-  if (budget < 0) got.flags |= kFlagTimeout;  // no wait at all
-  bool polled = false;
-  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  for (int s = threadIdx.x; s < nb && budget >= 0; s += blockDim.x) {
-    // Epochs only grow; a slot written for a later epoch also counts as arrived
-    // (its payload lives in the other parity buffer).
-    while ((int32_t)(__hip_atomic_load(&buf[s].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
-      __builtin_amdgcn_s_sleep(1);
-      // Watchdog: a barrier that has not completed after `budget` ticks of
-      // the 100 MHz real-time counter reports a timeout instead of waiting
-      // forever.
-      if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)budget) {
-        got.flags |= kFlagTimeout;
-        break;
+  // Wave 0 alone polls every slot, acquires and reduces the candidates; the
+  // other waves wait at one workgroup barrier for the result.  (Measured
+  // against four polling waves and a block reduction: 1024 x 8192 3-4 %
+  // faster, 4096^2 0.5-1.6 %, 8192^2 unchanged.)
+  Cand* const result = scratch + (kCandScratch - 1);  // not used by block_reduce
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    Cand got = cand_none();
+    if (budget < 0) got.flags |= kFlagTimeout;  // no wait at all
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int s = lane; s < nb && budget >= 0; s += kWave) {
+      // Epochs only grow; a slot written for a later epoch also counts as
+      // arrived (its payload lives in the other parity buffer).
+      while ((int32_t)(__hip_atomic_load(&buf[s].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+        __builtin_amdgcn_s_sleep(1);
+        // Watchdog: a barrier that has not completed after `budget` ticks of
+        // the 100 MHz real-time counter reports a timeout instead of waiting
+        // forever.
+        if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)budget) {
+          got.flags |= kFlagTimeout;
+          break;
+        }
       }
     }
-    polled = true;
-  }
-  (void)polled;
-  // One agent-scope acquire per workgroup (it invalidates this CU's L1 and
-  // the XCD's L2, which every wave of the workgroup shares), after every
-  // slot has been seen and before any wave reads a payload.
-  __syncthreads();
-  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  __syncthreads();
-  if (tk && threadIdx.x == 0) tk[5] = __builtin_amdgcn_s_memrealtime();
-  uint64_t ta = 0, tp = 0;
-  for (int s = threadIdx.x; s < nb; s += blockDim.x) {
-    Cand o;
-    o.v = buf[s].v;
-    o.aux = buf[s].aux;
-    o.i = buf[s].i;
-    o.flags = buf[s].flags;
-    got = cand_merge(got, o);
+    // One agent-scope acquire per workgroup, after every slot has been seen
+    // and before any payload is read: it invalidates this CU's L1 and the
+    // XCD's L2, which the other waves share; they read nothing written by
+    // other workgroups before the workgroup barrier below.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tk && lane == 0) tk[5] = __builtin_amdgcn_s_memrealtime();
+    uint64_t ta = 0, tp = 0;
+    for (int s = lane; s < nb; s += kWave) {
+      Cand o;
+      o.v = buf[s].v;
+      o.aux = buf[s].aux;
+      o.i = buf[s].i;
+      o.flags = buf[s].flags;
+      got = cand_merge(got, o);
+      if (tk) {
+        ta = max(ta, buf[s].t_arrive);
+        tp = max(tp, buf[s].t_pub);
+      }
+    }
     if (tk) {
-      ta = max(ta, buf[s].t_arrive);
-      tp = max(tp, buf[s].t_pub);
+      // Diagnostics only: latest arrival and latest publication over all workgroups.
+      for (int msk = kWave / 2; msk > 0; msk >>= 1) {
+        ta = max(ta, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, ta), msk)));
+        tp = max(tp, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, tp), msk)));
+      }
+      if (lane == 0 && ta) {
+        __hip_atomic_fetch_max(tk + 3, ta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_max(tk + 4, tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
-  }
-  if (tk) {
-    // Diagnostics only: latest arrival and latest publication over all workgroups.
-    for (int msk = kWave / 2; msk > 0; msk >>= 1) {
-      ta = max(ta, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, ta), msk)));
-      tp = max(tp, __builtin_bit_cast(uint64_t, shfl_xor_d(__builtin_bit_cast(double, tp), msk)));
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0 && ta) {
-      __hip_atomic_fetch_max(tk + 3, ta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_max(tk + 4, tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
+    got = wave_reduce(got);
+    if (lane == 0) *result = got;
   }
   __syncthreads();
-  const Cand r = block_reduce(got, scratch);
+  // The result is the same in every lane: make that explicit (scalar registers).
+  Cand r = *result;
+  r.v = __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, r.v)));
+  r.aux = __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, r.aux)));
+  r.i = __builtin_amdgcn_readfirstlane(r.i);
+  r.flags = __builtin_amdgcn_readfirstlane(r.flags);
   if (tk && threadIdx.x == 0) tk[6] = __builtin_amdgcn_s_memrealtime();
   return r;
 }
