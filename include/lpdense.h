@@ -43,6 +43,12 @@
  * Thread safety: calls on distinct streams may run concurrently; the library
  * keeps no mutable global state apart from per-device launch limits that are
  * computed once.
+ *
+ * Processes: the grid schedules, lp_solve_batch and the server launch
+ * cooperatively (every workgroup co-resident).  Use one process per device
+ * for them: a second process's grid launch was seen to fail with
+ * LPD_ERR_HIP once another process had launched cooperatively on the same
+ * device.
  */
 #ifndef LPDENSE_H
 #define LPDENSE_H
