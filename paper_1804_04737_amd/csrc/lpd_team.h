@@ -14,7 +14,8 @@
 //        publishes one slice of the new objective row and pivot row.
 //   Q_t  (all workgroups, flat grid-stride over constraint rows x 16-byte
 //        vectors)  T[i,:] <- fma(-f_i, r, T[i,:]) for i != l_t (Step 5),
-//        streamed once with non-temporal 128-bit loads and stores.  The
+//        streamed once with 128-bit loads (non-temporal, or temporal on
+//        tableaux the memory-side cache holds) and non-temporal stores.  The
 //        thread that meets element (i, k_{t+1}) forms the new entering-column
 //        entry and right-hand side of row i and appends them to an LDS list;
 //        after the sweep the workgroup forms the ratios (Step 3 of the next
