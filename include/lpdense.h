@@ -178,6 +178,9 @@ typedef struct lpd_outputs {
     int64_t phase_cap;     /* capacity of phase_ticks in pivots */
 } lpd_outputs;
 
+/* The same struct under the name lpd_result. */
+typedef lpd_outputs lpd_result;
+
 /*
  * lp_solve_dense_ex: solve one LP with options and optional outputs.
  * `prob`, `opt` and `out` are host structs read during the call; `opt` may be
