@@ -114,13 +114,48 @@ def host_triad_gbps(threads: int, mib: int = 1024, reps: int = 5):
         torch.set_num_threads(prev)
 
 
-def cpu_baseline(A, b, c, target_s: float, samples: int = 3):
-    """The CPU oracle on this host (a reported baseline, never the target):
-    with every physical core this process may use (the OpenMP build of the
-    same source: Step 5's rows in threads, every value unchanged) and with one
-    thread; median of `samples` samples each."""
+def cpu_baseline(m: int, n: int, seed: int, generator: str, target_s: float, samples: int = 3):
+    """The CPU oracle on this host (a reported baseline, never the target),
+    timed in a child process that touches no GPU, with the OpenMP threads
+    pinned to cores (OMP_PROC_BIND=close, OMP_PLACES=cores unless set): the
+    OpenMP runtime reads those when it starts, and in this process it
+    started with torch."""
+    import subprocess
+    env = dict(os.environ)
+    env.setdefault("OMP_PROC_BIND", "close")
+    env.setdefault("OMP_PLACES", "cores")
+    # The host as this (unpinned) process sees it: the child's OpenMP runtime
+    # binds its initial thread to one core as it starts.
+    spec = json.dumps({"m": m, "n": n, "seed": seed, "generator": generator, "target_s": target_s,
+                       "samples": samples, "host": host_cpu()})
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", spec], env=env,
+                       capture_output=True, text=True, timeout=max(300.0, 4 * target_s))
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU baseline child failed ({r.returncode}): {r.stderr[-2000:]}")
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    out["pinning"] = f"OMP_PROC_BIND={env['OMP_PROC_BIND']} OMP_PLACES={env['OMP_PLACES']}"
+    return out
+
+
+def _cpu_baseline_child(spec: str):
+    """Body of cpu_baseline in its child: the same LP from the generator, the
+    oracle with every physical core this process may use (the OpenMP build of
+    the same source: Step 5's rows in threads, every value unchanged) and with
+    one thread, median of `samples` samples each; one JSON line."""
+    q = json.loads(spec)
+    # torch first: the oracle's OpenMP build then shares torch's OpenMP
+    # runtime (pinned from this process's environment) instead of starting a
+    # second one whose idle threads would spin beside torch's during the
+    # triad.
+    import torch  # noqa: F401
+    from paper_1804_04737_amd import lpgen
+    gen = lpgen.paper_lp if q["generator"] == "paper" else lpgen.dense_lp
+    A, b, c = gen(q["m"], q["n"], q["seed"])
+    print(json.dumps(_cpu_baseline_here(A, b, c, q["target_s"], q["samples"], q["host"])), flush=True)
+
+
+def _cpu_baseline_here(A, b, c, target_s: float, samples: int, host: dict):
     import oracle
-    host = host_cpu()
     omp_env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     threads = min(host["physical_cores"], host["logical_cpus_allowed"])
     if omp_env > 0:
@@ -749,7 +784,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(A, b, c, args.cpu_seconds)
+        cpu = cpu_baseline(m, n, args.seed, args.generator, args.cpu_seconds)
 
     out = {
         "metric": METRIC,
@@ -789,4 +824,7 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) == 3 and sys.argv[1] == "--cpu-baseline-child":
+        _cpu_baseline_child(sys.argv[2])
+    else:
+        main()
