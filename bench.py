@@ -225,6 +225,24 @@ def single_schedule(m, n, full_tableau):
     return lpdense.SCHED_GRID_CONDENSED
 
 
+def batch_cpu_baseline(lps, threads: int):
+    """The batched LPs on this host's cores, one LP per thread at a time (the
+    serial oracle, whose ctypes calls release the GIL): the batch's reported
+    CPU baseline, as the paper's shared-memory machine would run independent
+    LPs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    oracle.solve(*lps[0])  # load the library outside the timed region
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        statuses = list(ex.map(lambda lp: oracle.solve(*lp).status, lps))
+    el = time.perf_counter() - t0
+    return {"LPs_per_s": round(len(lps) / el, 2), "seconds": round(el, 3), "threads": threads, "kind": "oracle",
+            "statuses_optimal": int(sum(1 for x in statuses if x == oracle.OPTIMAL)),
+            "sample": f"all {len(lps)} LPs of the batch, full tableau, one thread per LP"}
+
+
 def batch_summary(args, steps: int, warmup: int):
     """Batched workload: one lp_solve_batch call on 1024 LPs with m, n
     log-uniform in [32, 1024] (seed 0) per step, against solving the same
@@ -274,6 +292,13 @@ def batch_summary(args, steps: int, warmup: int):
     el1 = time.perf_counter() - t0
     single_lps_s = pb.count / el1
     log(f"one at a time: {el1 * 1e3:.1f} ms for {pb.count} LPs, {single_lps_s:.1f} LPs/s")
+    cpu = None
+    if not getattr(args, "no_cpu_baseline", False):
+        host = host_cpu()
+        threads = min(host["physical_cores"], host["logical_cpus_allowed"])
+        omp_env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+        cpu = batch_cpu_baseline(lps, min(threads, omp_env) if omp_env > 0 else threads)
+        log(f"CPU oracle, {cpu['threads']} threads: {cpu['LPs_per_s']:.1f} LPs/s")
     tr = None
     if (args.batch_count, args.batch_lo, args.batch_hi, args.seed) == (1024, 32, 1024, 0) and not args.full_tableau \
             and (args.team_size, args.team_min_bytes, args.wave_slots) == (0, 0, 0):
@@ -290,7 +315,8 @@ def batch_summary(args, steps: int, warmup: int):
             "one_at_a_time_effective_GBps": round(bytes_step / el1 / 1e9, 1),
             "speedup_vs_one_at_a_time": round(lps_s / single_lps_s, 2),
             "team_size": args.team_size, "team_min_bytes": args.team_min_bytes,
-            "wave_slots": args.wave_slots, "tableau": "full" if args.full_tableau else "condensed"}
+            "wave_slots": args.wave_slots, "tableau": "full" if args.full_tableau else "condensed",
+            "cpu_baseline": cpu, "speedup_vs_cpu_baseline": None if cpu is None else round(lps_s / cpu["LPs_per_s"], 1)}
 
 
 def batch_bench(args):
