@@ -89,9 +89,10 @@ def test_tableau_after_k_pivots(m, n, K, schedule):
 
 
 @GRIDS
-@pytest.mark.parametrize("blocks", [1, 2, 3, 7, 64, 255, 0])
+@pytest.mark.parametrize("blocks", [1, 2, 3, 7, 64, 255, 256, 512, 0])
 def test_grid_size_invariance(blocks, schedule):
-    """Any grid size gives the same bits (a race would show up as a difference)."""
+    """Any grid size gives the same bits (a race would show up as a difference);
+    sizes past the co-resident limit are clamped to it."""
     A, b, c = lpgen.dense_lp(300, 451, 5)
     announce(f"grid blocks={blocks} 300x451 schedule={schedule}")
     g = gpu_solve(A, b, c, schedule=schedule, grid_blocks=blocks, want_tableau=True)
