@@ -167,3 +167,27 @@ def test_schedule_constants_match_header():
         "LPD_SCHED_GRID_PAIRED": lpdense.SCHED_GRID_PAIRED,
         "LPD_SCHED_GRID_CONDENSED_PAIRED": lpdense.SCHED_GRID_CONDENSED_PAIRED,
     }
+
+
+@pytest.mark.parametrize("lang,std", [("c", "c99"), ("c++", "c++11")])
+def test_header_compiles_standalone(lang, std):
+    """The public header builds on its own as C99 and as C++11 with warnings as errors,
+    and lpd_result names the outputs struct."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    code = ('#include "lpdense.h"\n'
+            "int main(void) { lpd_result r; lpd_outputs *o = &r; (void)o;\n"
+            "  int (*f)(const lpd_problem*, const lpd_options*, const lpd_outputs*, hipStream_t)"
+            " = lp_solve_dense_ex; (void)f; return 0; }\n")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "h.c")
+        open(src, "w").write(code)
+        r = subprocess.run([cc, "-x", lang, f"-std={std}", "-Wall", "-Wextra", "-Werror",
+                            "-D__HIP_PLATFORM_AMD__", f"-I{os.path.dirname(HEADER)}",
+                            "-I/opt/rocm/include", "-c", src, "-o", os.path.join(d, "h.o")],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-2000:]
