@@ -13,10 +13,19 @@
 
 namespace lpd {
 
-constexpr int kWgScratch = 1024 / kWave + 1;  // block-reduction scratch entries (any NT <= 1024)
+// Small control block in LDS: the pivot the group's leading wave chose, or
+// the status that ends the solve.
+struct WgCtrl {
+  double p;
+  int32_t k, l, status, pad;
+};
+
+// LDS after the tableau: the entering column, the basis, one partial
+// arg-min per wave (any NT <= 1024) and the control block.
+constexpr int kWgWaves = 1024 / kWave;
 
 struct WgLayout {
-  size_t off_T, off_pcol, off_basis, off_scratch, total;
+  size_t off_T, off_pcol, off_basis, off_scratch, off_ctrl, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -28,21 +37,20 @@ __host__ __device__ inline WgLayout wg_layout(int64_t m, int64_t n) {
   L.off_pcol = align16(R * W * 8);
   L.off_basis = L.off_pcol + align16(R * 8);
   L.off_scratch = L.off_basis + align16((size_t)m * 4);
-  L.total = L.off_scratch + kWgScratch * sizeof(Cand);
+  L.off_ctrl = L.off_scratch + kWgWaves * sizeof(Cand);
+  L.total = L.off_ctrl + sizeof(WgCtrl);
   return L;
 }
 
 // Thread groups that can run the LDS solve: a whole workgroup of NT threads,
 // or one wave on its own slice of the workgroup's LDS (several small LPs per
-// workgroup, one per wave).
+// workgroup, one per wave).  Wave 0 of the group takes the decisions.
 template <int NT>
 struct BlockGroup {
   static constexpr int kThreads = NT;
   __device__ static int rank() { return threadIdx.x; }
   // LDS writes before, reads after.
   __device__ static void sync() { __syncthreads(); }
-  // Arg-min over the group; also orders the LDS writes made before it.
-  __device__ static Cand reduce(Cand c, Cand* scratch) { return block_reduce(c, scratch); }
   // Global stores before complete before those after.
   __device__ static void order_global() { __syncthreads(); }
 };
@@ -55,113 +63,258 @@ struct WaveGroup {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
-  __device__ static Cand reduce(Cand c, Cand*) {
-    sync();
-    return wave_reduce(c);
-  }
   __device__ static void order_global() {
     __builtin_amdgcn_s_waitcnt(0);
     sync();
   }
 };
 
+// Wave arg-min for the LDS solve, equal to the lexicographic (value, index)
+// arg-min on candidates that are never NaN: the least value (v_min), then
+// the least index among the lanes that hold a value equal to it, then the
+// payload of the lowest such lane.  All lanes must be active; every lane
+// gets the result.  ROWS16: only lanes 0-15 hold candidates (the others
+// must hold cand_none), and the reduction stays within the first row of 16.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_min_d(double v) {
+  int2 q = __builtin_bit_cast(int2, v);
+  q.x = __builtin_amdgcn_update_dpp(q.x, q.x, CTRL, ROW_MASK, 0xF, false);
+  q.y = __builtin_amdgcn_update_dpp(q.y, q.y, CTRL, ROW_MASK, 0xF, false);
+  return __builtin_fmin(v, __builtin_bit_cast(double, q));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_min_i(int32_t x) {
+  return min(x, __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xF, false));
+}
+
+template <bool ROWS16>
+__device__ __forceinline__ Cand wave_argmin(const Cand& c) {
+  constexpr int kLast = ROWS16 ? 15 : 63;
+  double v = c.v;
+  v = dpp_min_d<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v = dpp_min_d<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v = dpp_min_d<0x141, 0xF>(v);  // row_half_mirror
+  v = dpp_min_d<0x140, 0xF>(v);  // row_mirror
+  if (!ROWS16) {
+    v = dpp_min_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_min_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  }
+  const double vmin = readlane_d(v, kLast);
+  int32_t i = c.v == vmin ? c.i : kNoIndex;
+  i = dpp_min_i<0xB1, 0xF>(i);
+  i = dpp_min_i<0x4E, 0xF>(i);
+  i = dpp_min_i<0x141, 0xF>(i);
+  i = dpp_min_i<0x140, 0xF>(i);
+  if (!ROWS16) {
+    i = dpp_min_i<0x142, 0xA>(i);
+    i = dpp_min_i<0x143, 0xC>(i);
+  }
+  Cand r;
+  r.i = __builtin_amdgcn_readlane(i, kLast);
+  const uint64_t hit = __ballot(c.i == r.i && c.v == vmin);
+  const int lane = hit ? (int)__builtin_ctzll(hit) : 0;
+  r.v = readlane_d(c.v, lane);
+  r.aux = readlane_d(c.aux, lane);
+  r.flags = 0;
+  if (__ballot(c.flags & kFlagNonFinite)) r.flags |= kFlagNonFinite;
+  if (__ballot(c.flags & kFlagNegativeB)) r.flags |= kFlagNegativeB;
+  return r;
+}
+
+// Elements per thread and batch in the flat walks over the tableau: their
+// loads are all issued before the first one is used.
+constexpr int kWgBatch = 4;
+
+// Position (row, column) of a flat tableau index, advanced by the group size
+// with a carry, so that the walks need no division per element.
+struct WgCursor {
+  int32_t i, j;
+  __device__ void step(int32_t di, int32_t dj, int32_t W) {
+    i += di;
+    j += dj;
+    if (j >= W) {
+      j -= W;
+      ++i;
+    }
+  }
+};
+
+// Per pivot: (1) every wave reduces the pricing offers its threads made on
+// the objective row into its partial; (2) after a barrier, wave 0 combines
+// the partials into the entering column k (Step 2), gathers column k into
+// pcol and runs the ratio test (Step 3), and publishes the pivot (or the
+// status) in the control block; (3) after a barrier, the group divides row
+// l by the pivot (Step 4); (4) after a barrier, every thread eliminates
+// column k from its share of the other rows (Step 5) and prices its share
+// of the updated objective row for the next pivot.  Three workgroup
+// barriers per pivot; the decisions take one wave and no cross-wave
+// reduction.
 template <class Grp>
 __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   constexpr int NT = Grp::kThreads;
-  const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m, W = ncols + 1, R = m + 1;
+  constexpr int U = kWgBatch;
+  const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m, W = ncols + 1, R = m + 1, RW = R * W;
   const WgLayout L = wg_layout(m, n);
   double* T = reinterpret_cast<double*>(smem + L.off_T);
   double* pcol = reinterpret_cast<double*>(smem + L.off_pcol);
   int32_t* basis = reinterpret_cast<int32_t*>(smem + L.off_basis);
-  Cand* scratch = reinterpret_cast<Cand*>(smem + L.off_scratch);
-  const int tid = Grp::rank(), lane = tid & (kWave - 1), wave = tid / kWave, nw = NT / kWave;
+  Cand* part = reinterpret_cast<Cand*>(smem + L.off_scratch);
+  WgCtrl* ctrl = reinterpret_cast<WgCtrl*>(smem + L.off_ctrl);
+  const int tid = Grp::rank(), lane = tid & (kWave - 1), wave = tid / kWave;
+  constexpr int nw = NT / kWave;
+  // Flat walks: thread tid takes elements tid, tid + NT, ... of the row-major
+  // R x W tableau.
+  const int32_t di = NT / W, dj = NT % W;
+  const WgCursor first{tid / W, tid % W};
+  double* Tm = T + (size_t)m * W;
 
   // Step 1: Table 1 layout, RHS in column W-1, objective row last; or (T0)
   // a given basic tableau of that layout, its right-hand side unchecked.
-  int32_t flags = 0;
-  for (int32_t i = wave; i < R; i += nw) {
-    double* Ti = T + (size_t)i * W;
-    for (int32_t j = lane; j < W; j += kWave) {
-      double v;
-      if (a.T0) {
-        v = a.T0[(int64_t)i * W + j];
-      } else if (i < m) {
-        if (j < n) v = a.A[(int64_t)i * n + j];
-        else if (j < ncols) v = (j - n == i) ? 1.0 : 0.0;
-        else {
-          v = a.b[i];
-          if (v < 0.0) flags |= kFlagNegativeB;
-        }
-      } else {
-        v = j < n ? -a.c[j] : 0.0;
+  // With it, the pricing offers of the initial objective row.
+  Cand pc = cand_none();
+  {
+    const double* dummy = a.T0 ? a.T0 : a.b;
+    WgCursor cur = first;
+    for (int32_t e0 = tid; e0 < RW; e0 += U * NT) {
+      // Every lane loads (from the first entry of T0, else of b, where the
+      // entry is a constant or past the end), so that the batch's loads are
+      // issued back to back.  T0 comes without b.
+      double v[U], k[U];
+      bool ld[U];
+      int32_t ri[U], cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t e = e0 + u * NT, i = cur.i, j = cur.j;
+        ri[u] = i;
+        cj[u] = j;
+        cur.step(di, dj, W);
+        const double* src = dummy;
+        ld[u] = e < RW;
+        k[u] = 0.0;
+        if (a.T0) src = a.T0 + e;
+        else if (i < m) {
+          if (j < n) src = a.A + (int64_t)i * n + j;
+          else if (j == ncols) src = a.b + i;
+          else ld[u] = false, k[u] = (j - n == i) ? 1.0 : 0.0;
+        } else if (j < n) src = a.c + j;
+        else ld[u] = false;
+        if (!ld[u]) src = dummy;
+        v[u] = *src;
       }
-      if (!is_finite(v)) flags |= kFlagNonFinite;
-      Ti[j] = v;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t e = e0 + u * NT;
+        if (e >= RW) continue;
+        double x = ld[u] ? v[u] : k[u];
+        if (!a.T0 && ri[u] == m && cj[u] < n) x = -x;
+        if (!is_finite(x)) pc.flags |= kFlagNonFinite;
+        if (!a.T0 && ri[u] < m && cj[u] == ncols && x < 0.0) pc.flags |= kFlagNegativeB;
+        if (ri[u] == m && cj[u] < ncols && !__builtin_isnan(x)) cand_offer(pc, x, cj[u], 0.0);
+        T[e] = x;
+      }
     }
   }
   for (int32_t i = tid; i < m; i += NT) basis[i] = a.T0 ? a.basis0[i] : n + i;
-  Cand fc = cand_none();
-  fc.flags = flags;
-  fc = Grp::reduce(fc, scratch);
 
   int32_t status = -1;
-  if (fc.flags & kFlagNonFinite) status = kNumerical;
-  else if (fc.flags & kFlagNegativeB) status = kInfeasibleStart;
-
   int64_t iter = 0;
-  double* Tm = T + (size_t)m * W;
-  while (status < 0) {
-    // Step 2: most negative reduced cost, lowest index on ties.
-    Cand pc = cand_none();
-    for (int32_t j = tid; j < ncols; j += NT) {
-      const double v = Tm[j];
-      if (!is_finite(v)) pc.flags |= kFlagNonFinite;
-      if (!__builtin_isnan(v)) cand_offer(pc, v, j, 0.0);
-    }
-    pc = Grp::reduce(pc, scratch);
-    if (pc.flags & kFlagNonFinite) { status = kNumerical; break; }
-    if (pc.v >= -a.eps_d) { status = kOptimal; break; }
-    if (iter == a.max_iter) { status = kIterLimit; break; }
-    const int32_t k = pc.i;
+  for (;;) {
+    // (1) This wave's partial of the pricing offers (and of the flags).
+    if (__ballot(pc.i != kNoIndex || pc.flags != 0)) pc = wave_argmin<false>(pc);
+    if (lane == 0) part[wave] = pc;
+    Grp::sync();
 
-    // Step 3: min ratio over rows with T[i,k] > eps_p, lowest row on ties.
-    Cand rc = cand_none();
-    for (int32_t i = tid; i < R; i += NT) {
-      const double aik = T[(size_t)i * W + k];
-      pcol[i] = aik;
-      if (i < m) {
-        const double r = T[(size_t)i * W + W - 1];
-        if (!is_finite(aik) || !is_finite(r)) rc.flags |= kFlagNonFinite;
-        if (aik > a.eps_p) cand_offer(rc, r / aik, i, aik);
+    // (2) Wave 0: Steps 2 and 3, then the control block.
+    if (wave == 0) {
+      WgCtrl cb{0.0, 0, 0, -1, 0};
+      Cand q = lane < nw ? part[lane] : cand_none();
+      q = wave_argmin<true>(q);
+      if (iter == 0 && (q.flags & kFlagNegativeB) && !(q.flags & kFlagNonFinite)) cb.status = kInfeasibleStart;
+      else if (q.flags & kFlagNonFinite) cb.status = kNumerical;
+      else if (q.v >= -a.eps_d) cb.status = kOptimal;
+      else if (iter == a.max_iter) cb.status = kIterLimit;
+      if (cb.status < 0) {
+        const int32_t k = q.i;
+        Cand rc = cand_none();
+        for (int32_t i0 = lane; i0 < R; i0 += U * kWave) {
+          double aik[U], rhs[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int32_t i = min(i0 + u * kWave, m);
+            aik[u] = T[(size_t)i * W + k];
+            rhs[u] = T[(size_t)i * W + W - 1];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int32_t i = i0 + u * kWave;
+            if (i >= R) continue;
+            pcol[i] = aik[u];
+            if (i < m) {
+              if (!is_finite(aik[u]) || !is_finite(rhs[u])) rc.flags |= kFlagNonFinite;
+              if (aik[u] > a.eps_p) cand_offer(rc, rhs[u] / aik[u], i, aik[u]);
+            }
+          }
+        }
+        rc = wave_argmin<false>(rc);
+        if (rc.flags & kFlagNonFinite) cb.status = kNumerical;
+        else if (rc.i == kNoIndex) cb.status = kUnbounded;
+        else cb = WgCtrl{rc.aux, k, rc.i, -1, 0};
+      }
+      if (lane == 0) {
+        *ctrl = cb;
+        if (cb.status < 0) {
+          basis[cb.l] = cb.k;
+          if (iter < a.trace_cap && a.trace) {
+            a.trace[2 * iter] = cb.k;
+            a.trace[2 * iter + 1] = cb.l;
+          }
+        }
       }
     }
-    rc = Grp::reduce(rc, scratch);  // orders the pcol writes too
-    if (rc.flags & kFlagNonFinite) { status = kNumerical; break; }
-    if (rc.i == kNoIndex) { status = kUnbounded; break; }
-    const int32_t l = rc.i;
-    const double p = rc.aux;
+    Grp::sync();
+    const WgCtrl cb = *ctrl;
+    status = __builtin_amdgcn_readfirstlane(cb.status);
+    if (status >= 0) break;
+    const int32_t l = __builtin_amdgcn_readfirstlane(cb.l);
+    const double p = __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, cb.p)));
 
-    // Step 4: divide the pivot row by the pivot.
+    // (3) Step 4: divide the pivot row by the pivot.
     double* Tl = T + (size_t)l * W;
     for (int32_t j = tid; j < W; j += NT) Tl[j] = Tl[j] / p;
     Grp::sync();
 
-    // Step 5: eliminate column k from every other row (objective row too).
-    for (int32_t i = wave; i < R; i += nw) {
-      if (i == l) continue;
-      double* Ti = T + (size_t)i * W;
-      const double f = pcol[i];
-      for (int32_t j = lane; j < W; j += kWave) Ti[j] = __builtin_fma(-f, Tl[j], Ti[j]);
-    }
-    if (tid == 0) {
-      basis[l] = k;
-      if (iter < a.trace_cap && a.trace) {
-        a.trace[2 * iter] = k;
-        a.trace[2 * iter + 1] = l;
+    // (4) Step 5: eliminate column k from every other row (objective row
+    // too), and price this thread's share of the updated objective row.
+    pc = cand_none();
+    WgCursor cur = first;
+    for (int32_t e0 = tid; e0 < RW; e0 += U * NT) {
+      double t[U], r[U], f[U];
+      int32_t ri[U], cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ri[u] = cur.i;
+        cj[u] = cur.j;
+        cur.step(di, dj, W);
+        // Past the end: load a valid element (and store nothing).
+        const int32_t e = min(e0 + u * NT, RW - 1);
+        t[u] = T[e];
+        r[u] = Tl[cj[u]];
+        f[u] = pcol[min(ri[u], m)];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t e = e0 + u * NT;
+        const double v = __builtin_fma(-f[u], r[u], t[u]);
+        if (e >= RW || ri[u] == l) continue;
+        T[e] = v;
+        if (ri[u] == m && cj[u] < ncols) {
+          if (!is_finite(v)) pc.flags |= kFlagNonFinite;
+          if (!__builtin_isnan(v)) cand_offer(pc, v, cj[u], 0.0);
+        }
       }
     }
     ++iter;
-    Grp::sync();
   }
 
   // Read-out: x from the basic rows' RHS, objective value, duals.
@@ -175,7 +328,7 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
     if (a.basis_out) a.basis_out[i] = bv;
   }
   if (a.tableau_out)
-    for (int32_t e = tid; e < R * W; e += NT) a.tableau_out[e] = T[e];
+    for (int32_t e = tid; e < RW; e += NT) a.tableau_out[e] = T[e];
   if (tid == 0) {
     *a.obj = Tm[W - 1];
     *a.status = status;
