@@ -51,6 +51,18 @@ def test_config0_64x64_workgroup(seed):
     assert_bitwise_equal(g, ref, check_tableau=True)
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 6000), (3, 1500), (7, 900), (120, 10), (100, 40), (33, 31)])
+def test_lds_shapes(m, n):
+    """The LDS schedule on shapes that stress its walks: rows longer than the
+    workgroup (a thread holds several columns of one row), more rows than a
+    wave has lanes, a tableau near the LDS limit, and tiny ones."""
+    A, b, c = lpgen.dense_lp(m, n, m + n)
+    announce(f"LDS schedule {m}x{n}")
+    g = gpu_solve(A, b, c, schedule=WG, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
 @GRIDS
 @pytest.mark.parametrize("seed", range(20))
 def test_config0_64x64_grid(seed, schedule):
