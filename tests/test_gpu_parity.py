@@ -63,6 +63,24 @@ def test_lds_shapes(m, n):
     assert_bitwise_equal(g, ref, check_tableau=True)
 
 
+@pytest.mark.parametrize("schedule", [WG, GRID, CD, PAIR, CDPAIR],
+                         ids=["wg", "grid", "condensed", "paired", "condensed_paired"])
+@pytest.mark.parametrize("m,n,lo,hi,bv,cv", [(50, 60, 1, 3, 6.0, 5.0), (64, 64, 1, 2, 4.0, 1.0),
+                                             (30, 90, 0, 2, 2.0, 3.0)])
+def test_heavy_ties(m, n, lo, hi, bv, cv, schedule):
+    """Every reduced cost equal at the start, A of a few small integers (some
+    zero) and a constant b: many exact ties in pricing and in the ratio test,
+    and degenerate pivots; the lowest index must win each of them."""
+    rng = np.random.default_rng(7 + m + n)
+    A = rng.integers(lo, hi + 1, size=(m, n)).astype(float)
+    b, c = np.full(m, bv), np.full(n, cv)
+    announce(f"heavy ties {m}x{n} schedule={schedule}")
+    g = gpu_solve(A, b, c, schedule=schedule, want_tableau=True)
+    ref = oracle.solve(A, b, c, want_tableau=True)
+    assert ref.status == oracle.OPTIMAL
+    assert_bitwise_equal(g, ref, check_tableau=True)
+
+
 @GRIDS
 @pytest.mark.parametrize("seed", range(20))
 def test_config0_64x64_grid(seed, schedule):
