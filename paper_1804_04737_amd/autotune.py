@@ -18,8 +18,9 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 
 
-def sweep(count=1024, seed=0, fixed_sizes=(2, 4, 8), per_wg=(1 << 18, 1 << 19, 1 << 20, 2 << 20, 4 << 20),
-          thresholds=(1 << 19, 1 << 20, 2 << 20, 4 << 20), reps=3, log=print):
+def sweep(count=1024, seed=0, fixed_sizes=(2, 4, 8),
+          per_wg=(1 << 18, 3 << 17, 1 << 19, 3 << 18, 1 << 20, 2 << 20, 4 << 20),
+          thresholds=(1 << 18, 1 << 19, 1 << 20, 2 << 20, 4 << 20), reps=3, log=print):
     """Time lp_solve_batch for every knob setting; returns (best, all)."""
     import numpy as np
     import torch
