@@ -20,9 +20,14 @@ struct WgCtrl {
   int32_t k, l, status, pad;
 };
 
-// LDS after the tableau: the entering column, the basis, one partial
-// arg-min per wave (any NT <= 1024) and the control block.
+// LDS: the tableau with rows padded to an even number of doubles (16-byte
+// aligned rows, so that the update moves two columns per access; the pad
+// column holds zero and is never read as data), then the entering column,
+// the basis, one partial arg-min per wave (any NT <= 1024) and the control
+// block.
 constexpr int kWgWaves = 1024 / kWave;
+
+__host__ __device__ inline int64_t wg_ldw(int64_t W) { return (W + 1) & ~int64_t(1); }
 
 struct WgLayout {
   size_t off_T, off_pcol, off_basis, off_scratch, off_ctrl, total;
@@ -31,10 +36,10 @@ struct WgLayout {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline WgLayout wg_layout(int64_t m, int64_t n) {
-  const size_t R = (size_t)m + 1, W = (size_t)(n + m + 1);
+  const size_t R = (size_t)m + 1, ldw = (size_t)wg_ldw(n + m + 1);
   WgLayout L;
   L.off_T = 0;
-  L.off_pcol = align16(R * W * 8);
+  L.off_pcol = align16(R * ldw * 8);
   L.off_basis = L.off_pcol + align16(R * 8);
   L.off_scratch = L.off_basis + align16((size_t)m * 4);
   L.off_ctrl = L.off_scratch + kWgWaves * sizeof(Cand);
@@ -154,7 +159,8 @@ template <class Grp>
 __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   constexpr int NT = Grp::kThreads;
   constexpr int U = kWgBatch;
-  const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m, W = ncols + 1, R = m + 1, RW = R * W;
+  const int32_t m = (int32_t)a.m, n = (int32_t)a.n, ncols = n + m, W = ncols + 1, R = m + 1;
+  const int32_t ldw = (int32_t)wg_ldw(W), hw = ldw / 2, RL = R * ldw, RH = R * hw;
   const WgLayout L = wg_layout(m, n);
   double* T = reinterpret_cast<double*>(smem + L.off_T);
   double* pcol = reinterpret_cast<double*>(smem + L.off_pcol);
@@ -164,10 +170,11 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   const int tid = Grp::rank(), lane = tid & (kWave - 1), wave = tid / kWave;
   constexpr int nw = NT / kWave;
   // Flat walks: thread tid takes elements tid, tid + NT, ... of the row-major
-  // R x W tableau.
-  const int32_t di = NT / W, dj = NT % W;
-  const WgCursor first{tid / W, tid % W};
-  double* Tm = T + (size_t)m * W;
+  // R x ldw tableau (Step 1), or pairs of columns tid, tid + NT, ... of the
+  // R x ldw/2 pairs (Step 5).
+  const int32_t di = NT / ldw, dj = NT % ldw, pdi = NT / hw, pdj = NT % hw;
+  const WgCursor first{tid / ldw, tid % ldw}, pfirst{tid / hw, tid % hw};
+  double* Tm = T + (size_t)m * ldw;
 
   // Step 1: Table 1 layout, RHS in column W-1, objective row last; or (T0)
   // a given basic tableau of that layout, its right-hand side unchecked.
@@ -176,10 +183,10 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   {
     const double* dummy = a.T0 ? a.T0 : a.b;
     WgCursor cur = first;
-    for (int32_t e0 = tid; e0 < RW; e0 += U * NT) {
+    for (int32_t e0 = tid; e0 < RL; e0 += U * NT) {
       // Every lane loads (from the first entry of T0, else of b, where the
-      // entry is a constant or past the end), so that the batch's loads are
-      // issued back to back.  T0 comes without b.
+      // entry is a constant, the pad or past the end), so that the batch's
+      // loads are issued back to back.  T0 comes without b.
       double v[U], k[U];
       bool ld[U];
       int32_t ri[U], cj[U];
@@ -188,11 +195,11 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
         const int32_t e = e0 + u * NT, i = cur.i, j = cur.j;
         ri[u] = i;
         cj[u] = j;
-        cur.step(di, dj, W);
+        cur.step(di, dj, ldw);
         const double* src = dummy;
-        ld[u] = e < RW;
+        ld[u] = e < RL && j < W;
         k[u] = 0.0;
-        if (a.T0) src = a.T0 + e;
+        if (a.T0) src = a.T0 + (int64_t)i * W + j;
         else if (i < m) {
           if (j < n) src = a.A + (int64_t)i * n + j;
           else if (j == ncols) src = a.b + i;
@@ -205,7 +212,7 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t e = e0 + u * NT;
-        if (e >= RW) continue;
+        if (e >= RL) continue;
         double x = ld[u] ? v[u] : k[u];
         if (!a.T0 && ri[u] == m && cj[u] < n) x = -x;
         if (!is_finite(x)) pc.flags |= kFlagNonFinite;
@@ -242,8 +249,8 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int32_t i = min(i0 + u * kWave, m);
-            aik[u] = T[(size_t)i * W + k];
-            rhs[u] = T[(size_t)i * W + W - 1];
+            aik[u] = T[(size_t)i * ldw + k];
+            rhs[u] = T[(size_t)i * ldw + W - 1];
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
@@ -280,37 +287,47 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
     const double p = __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, cb.p)));
 
     // (3) Step 4: divide the pivot row by the pivot.
-    double* Tl = T + (size_t)l * W;
+    double* Tl = T + (size_t)l * ldw;
     for (int32_t j = tid; j < W; j += NT) Tl[j] = Tl[j] / p;
     Grp::sync();
 
     // (4) Step 5: eliminate column k from every other row (objective row
     // too), and price this thread's share of the updated objective row.
     pc = cand_none();
-    WgCursor cur = first;
-    for (int32_t e0 = tid; e0 < RW; e0 += U * NT) {
-      double t[U], r[U], f[U];
+    const dbl2* Tl2 = reinterpret_cast<const dbl2*>(Tl);
+    dbl2* T2 = reinterpret_cast<dbl2*>(T);
+    WgCursor cur = pfirst;
+    for (int32_t p0 = tid; p0 < RH; p0 += U * NT) {
+      dbl2 t[U], r[U];
+      double f[U];
       int32_t ri[U], cj[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         ri[u] = cur.i;
         cj[u] = cur.j;
-        cur.step(di, dj, W);
-        // Past the end: load a valid element (and store nothing).
-        const int32_t e = min(e0 + u * NT, RW - 1);
-        t[u] = T[e];
-        r[u] = Tl[cj[u]];
+        cur.step(pdi, pdj, hw);
+        // Past the end: load a valid pair (and store nothing).
+        t[u] = T2[min(p0 + u * NT, RH - 1)];
+        r[u] = Tl2[cj[u]];
         f[u] = pcol[min(ri[u], m)];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int32_t e = e0 + u * NT;
-        const double v = __builtin_fma(-f[u], r[u], t[u]);
-        if (e >= RW || ri[u] == l) continue;
-        T[e] = v;
-        if (ri[u] == m && cj[u] < ncols) {
-          if (!is_finite(v)) pc.flags |= kFlagNonFinite;
-          if (!__builtin_isnan(v)) cand_offer(pc, v, cj[u], 0.0);
+        dbl2 v;
+        v.x = __builtin_fma(-f[u], r[u].x, t[u].x);
+        v.y = __builtin_fma(-f[u], r[u].y, t[u].y);
+        if (p0 + u * NT >= RH || ri[u] == l) continue;
+        T2[p0 + u * NT] = v;
+        if (ri[u] == m) {
+          const int32_t j = 2 * cj[u];
+          if (j < ncols) {
+            if (!is_finite(v.x)) pc.flags |= kFlagNonFinite;
+            if (!__builtin_isnan(v.x)) cand_offer(pc, v.x, j, 0.0);
+          }
+          if (j + 1 < ncols) {
+            if (!is_finite(v.y)) pc.flags |= kFlagNonFinite;
+            if (!__builtin_isnan(v.y)) cand_offer(pc, v.y, j + 1, 0.0);
+          }
         }
       }
     }
@@ -323,12 +340,17 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   Grp::order_global();
   for (int32_t i = tid; i < m; i += NT) {
     const int32_t bv = basis[i];
-    if (bv < nx) a.x[bv] = T[(size_t)i * W + W - 1];
+    if (bv < nx) a.x[bv] = T[(size_t)i * ldw + W - 1];
     if (a.y) a.y[i] = Tm[n + i];
     if (a.basis_out) a.basis_out[i] = bv;
   }
-  if (a.tableau_out)
-    for (int32_t e = tid; e < RW; e += NT) a.tableau_out[e] = T[e];
+  if (a.tableau_out) {
+    WgCursor cur = first;  // over R x ldw; the pad column is not written out
+    for (int32_t e = tid; e < RL; e += NT) {
+      if (cur.j < W) a.tableau_out[(int64_t)cur.i * W + cur.j] = T[e];
+      cur.step(di, dj, ldw);
+    }
+  }
   if (tid == 0) {
     *a.obj = Tm[W - 1];
     *a.status = status;
