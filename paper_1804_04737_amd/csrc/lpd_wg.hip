@@ -25,9 +25,10 @@ __global__ void __launch_bounds__(kWave) wave_solve_kernel(SolveArgs a) {
 typedef void (*WgKernel)(SolveArgs);
 
 // Threads of the LDS solve, by tableau cells: 512 for tiny tableaux, 1024
-// from kWideCells on (measured, us per solve with 512 / 1024 threads:
-// 16 x 16 21.8 / 24.1, 32 x 32 20.9 / 20.7, 64 x 64 61.9 / 55.4,
-// 90 x 90 73.9 / 62.2; a single wave is 3-4x slower from 32 x 32 on).
+// from kWideCells on (measured, us per solve with 256 / 512 / 1024 threads:
+// 16 x 16 17.3 / 17.9 / 18.4, 32 x 32 17.4 / 14.5 / 14.4, 64 x 64
+// 59.1 / 45.3 / 38.9, 90 x 90 90.8 / 62.1 / 53.8; a single wave is 3-4x
+// slower from 32 x 32 on).
 // LPD_WG_THREADS (64, 256, 512 or 1024) overrides it, for tuning.
 constexpr int64_t kWideCells = 2000;
 int wg_threads(int64_t cells) {
