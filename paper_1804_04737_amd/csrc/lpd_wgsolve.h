@@ -8,6 +8,8 @@
 // eliminated element, lexicographic (value, index) arg-minima.
 #pragma once
 
+#include <type_traits>
+
 #include "lpd_device.h"
 #include "lpd_kernels.h"
 
@@ -174,6 +176,7 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
   // R x ldw/2 pairs (Step 5).
   const int32_t di = NT / ldw, dj = NT % ldw, pdi = NT / hw, pdj = NT % hw;
   const WgCursor first{tid / ldw, tid % ldw}, pfirst{tid / hw, tid % hw};
+  const int32_t full_batches = RH / (U * NT), tail_slots = (RH - full_batches * U * NT + NT - 1) / NT;
   double* Tm = T + (size_t)m * ldw;
 
   // Step 1: Table 1 layout, RHS in column W-1, objective row last; or (T0)
@@ -297,26 +300,30 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
     const dbl2* Tl2 = reinterpret_cast<const dbl2*>(Tl);
     dbl2* T2 = reinterpret_cast<dbl2*>(T);
     WgCursor cur = pfirst;
-    for (int32_t p0 = tid; p0 < RH; p0 += U * NT) {
-      dbl2 t[U], r[U];
-      double f[U];
-      int32_t ri[U], cj[U];
+    // One batch of UB slots (pairs p0, p0 + NT, ...), all loads issued
+    // first.  TAIL: some slots may lie past the end (they load a valid pair
+    // and store nothing); otherwise every slot is in range.
+    auto batch = [&](int32_t p0, auto ub, auto tail) {
+      constexpr int UB = decltype(ub)::value;
+      constexpr bool TAIL = decltype(tail)::value;
+      dbl2 t[UB], r[UB];
+      double f[UB];
+      int32_t ri[UB], cj[UB];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UB; ++u) {
         ri[u] = cur.i;
         cj[u] = cur.j;
         cur.step(pdi, pdj, hw);
-        // Past the end: load a valid pair (and store nothing).
-        t[u] = T2[min(p0 + u * NT, RH - 1)];
+        t[u] = T2[TAIL ? min(p0 + u * NT, RH - 1) : p0 + u * NT];
         r[u] = Tl2[cj[u]];
-        f[u] = pcol[min(ri[u], m)];
+        f[u] = pcol[TAIL ? min(ri[u], m) : ri[u]];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UB; ++u) {
         dbl2 v;
         v.x = __builtin_fma(-f[u], r[u].x, t[u].x);
         v.y = __builtin_fma(-f[u], r[u].y, t[u].y);
-        if (p0 + u * NT >= RH || ri[u] == l) continue;
+        if ((TAIL && p0 + u * NT >= RH) || ri[u] == l) continue;
         T2[p0 + u * NT] = v;
         if (ri[u] == m) {
           const int32_t j = 2 * cj[u];
@@ -330,6 +337,21 @@ __device__ void lds_solve(const SolveArgs& a, unsigned char* smem) {
           }
         }
       }
+    };
+    using no_tail = std::integral_constant<bool, false>;
+    using is_tail = std::integral_constant<bool, true>;
+    // Full batches (every thread's U slots in range), then one batch of as
+    // many slots as the rest needs, so that no thread walks a batch of
+    // empty slots.
+    int32_t p0 = tid;
+    for (int32_t bb = full_batches; bb > 0; --bb, p0 += U * NT) batch(p0, std::integral_constant<int, U>(), no_tail());
+    static_assert(U == 4, "the tail batch covers 1 to 4 slots");
+    switch (tail_slots) {
+      case 1: batch(p0, std::integral_constant<int, 1>(), is_tail()); break;
+      case 2: batch(p0, std::integral_constant<int, 2>(), is_tail()); break;
+      case 3: batch(p0, std::integral_constant<int, 3>(), is_tail()); break;
+      case 4: batch(p0, std::integral_constant<int, 4>(), is_tail()); break;
+      default: break;
     }
     ++iter;
   }
